@@ -1,0 +1,201 @@
+/*
+ * rh.h -- C ABI of the MI355X implementation of the coupled implicit
+ * radiation / ionisation / photoheating step of Norman, Reynolds & So,
+ * "Cosmological Radiation Hydrodynamics with Enzo" (arXiv:0908.2654).
+ *
+ * The step is the implicit subsystem of the paper's operator split
+ * (Algorithm section, step (v)): given the state U^n = (E, e, n_HI) at
+ * t_n, the hydrogen density n_H and the emissivity src = 4 pi eta, find
+ * U^{n+1} with f(U^{n+1}) = 0, where f stacks the gas-energy residual, the
+ * chemistry residual and the theta-method residual of the grey
+ * flux-limited-diffusion equation (equations gas_residual,
+ * chemistry_residual, radiation_residual; limiter from equation limiter;
+ * convergence in the RMS norm of equation rmsnorm).  Newton's linear
+ * systems are reduced by a Schur complement to a 7-point variable-
+ * coefficient diffusion system (the paper's "modified radiation
+ * equation"), solved by geometric multigrid V-cycles.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: nx*ny*nz cubic cells of comoving width h = box_comoving_cm/nx.
+ *  - Every field argument is a contiguous float64 array in device memory
+ *    of nx*ny*nz entries, C order [x][y][z] (z fastest, index
+ *    (i*ny + j)*nz + k), comoving CGS units:
+ *      E    radiation energy density      erg cm^-3
+ *      e    specific gas energy           erg g^-1
+ *      nHI  neutral hydrogen density      cm^-3
+ *      nH   total hydrogen density        cm^-3
+ *      src  4 pi eta (emissivity)         erg cm^-3 s^-1
+ *  - Device pointers must be distinct, 8-byte aligned and resident on the
+ *    device that was current at rh_setup.  The caller owns all device
+ *    memory, including the workspace; the library owns only its handle and
+ *    a few bytes of pinned host memory.  No entry point allocates device
+ *    memory after rh_setup.
+ *  - Work is enqueued on the stream given to rh_setup; calls return after
+ *    the last host-side convergence decision, with outputs complete on that
+ *    stream.  A handle is bound to one stream and is not thread safe.
+ *  - Every entry point returns an rh_status; rh_last_error gives the
+ *    message.  RH_EINVAL is returned before any device work is enqueued.
+ */
+#ifndef RH_H
+#define RH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RH_OK = 0,
+  RH_EINVAL = 1,     /* invalid parameter, size or pointer                        */
+  RH_ENOMEM = 2,     /* workspace smaller than rh_workspace_bytes                 */
+  RH_EHIP = 3,       /* a HIP runtime call failed                                 */
+  RH_ENONFINITE = 4, /* a residual or an input became NaN / Inf                   */
+  RH_ENEWTON = 5,    /* Newton or its line search did not converge                */
+  RH_ELINEAR = 6     /* the local per-cell solve or the linear solve broke down   */
+} rh_status;
+
+enum { RH_BC_ZEROFLUX = 0, RH_BC_PERIODIC = 1, RH_BC_OUTFLOW = 2 };
+enum { RH_SPEC_MONO = 0, RH_SPEC_BLACKBODY = 1 };
+enum { RH_RATES_CONST = 0, RH_RATES_FIT = 1 };
+enum { RH_COOL_RECB = 1, RH_COOL_COLLEXC = 2, RH_COOL_COMPTON = 4 };
+enum { RH_COSMO_STATIC = 0, RH_COSMO_EDS = 1, RH_COSMO_FLAT_LCDM = 2 };
+enum { RH_PREC_FP64 = 0, RH_PREC_MIXED = 1 };
+
+/* Problem and solver parameters (plain data, validated by rh_setup). */
+typedef struct rh_params {
+  int32_t nx, ny, nz;          /* grid; multigrid halves all three while they are even  */
+  int32_t bc[6];               /* per face x-, x+, y-, y+, z-, z+ (periodic in pairs)   */
+  double box_comoving_cm;      /* comoving x edge of the box                             */
+  int32_t isothermal;          /* 1: T fixed at T_iso_K, e is neither read nor written  */
+  int32_t spectrum;            /* RH_SPEC_*: grey constants (equation grey_definition)  */
+  double T_iso_K;
+  double T_bb_K;               /* blackbody temperature (paper: 1e5 K)                   */
+  double hnu0_eV;              /* ionisation threshold (13.6 eV)                         */
+  double sigma0_cm2;           /* threshold cross-section sigma(nu) = sigma0 (nu0/nu)^3  */
+  int32_t rates;               /* RH_RATES_CONST: alpha_B = alphaB_const; _FIT: fits     */
+  int32_t cooling_mask;        /* RH_COOL_* bits (ignored when isothermal)               */
+  double alphaB_const;         /* cm^3 s^-1 (paper: 2.59e-13)                            */
+  int32_t cosmology;           /* RH_COSMO_*: expansion factor a(t), Hubble rate H(t)    */
+  int32_t precision;           /* RH_PREC_FP64: all FP64; _MIXED: FP32 V-cycles inside  */
+                               /* FP64 defect correction                                 */
+  double hubble_h, Omega_m, Omega_L;
+  double theta;                /* time-centring of the theta method, (0, 1]; 1 = backward Euler */
+  double E_floor;              /* floor of face-mean E in the limiter (default 1e-40)    */
+  double R_min;                /* limiter floor on |grad E|/E; <= 0 selects 1/(a_n box)  */
+  double gamma;                /* ratio of specific heats (5/3)                          */
+  double newton_tol;           /* stop when ||f(U)|| <= newton_tol (RMS norm)            */
+  int32_t newton_max_it;       /* Newton iterations before RH_ENEWTON                    */
+  int32_t ls_max_cuts;         /* line-search halvings per iteration                     */
+  double lin_forcing;          /* linear solve to ||r|| <= lin_forcing ||f(U_k)|| (1e-13) */
+  int32_t lin_max_it;          /* outer (defect-correction) iterations per Newton step   */
+  int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps before / after coarsening */
+  int32_t mg_coarse_max;       /* stop coarsening at <= this many cells (<= 512)         */
+  int32_t krylov;              /* outer linear iteration: 1 = conjugate gradients with   */
+                               /* the V-cycle as preconditioner (default), 0 = plain     */
+                               /* defect correction x += V(b - S x)                      */
+} rh_params;
+
+/* Per-step statistics (host memory). */
+typedef struct rh_step_stats {
+  int32_t newton_its;          /* Newton iterations taken                                */
+  int32_t lin_its_total;       /* V-cycles over all Newton iterations                    */
+  int32_t ls_cuts;             /* line-search halvings                                   */
+  int32_t local_its_max;       /* most per-cell local Newton iterations in any call      */
+  double res0, res_final;      /* ||f|| at the start and at the end                      */
+  double lin_res_max;          /* largest final relative linear residual                 */
+  double t_ms[8];              /* GPU time per phase: 0 total, 1 setup, 2 local+residual, */
+                               /* 3 coarse setup, 4 V-cycles, 5 defect/accumulate        */
+} rh_step_stats;
+
+typedef struct rh_handle rh_handle;
+
+/* Fill p with the defaults (a 16^3 static zero-flux grid; every solver
+ * setting at its documented default).  Never fails. */
+void rh_default_params(rh_params* p);
+
+/* Bytes of device workspace rh_setup needs for p, or 0 if p is invalid. */
+size_t rh_workspace_bytes(const rh_params* p);
+
+/* Validate p, compute the grey constants (grey_definition, host FP64
+ * quadrature), plan the multigrid levels and carve the workspace.
+ * workspace: device memory of ws_bytes >= rh_workspace_bytes(p), owned by
+ * the caller and untouched by it while the handle lives.  hip_stream: a
+ * hipStream_t (NULL = default stream).  *out receives the handle. */
+rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* hip_stream,
+                   rh_handle** out);
+
+/* One implicit step from t_n to t_n + dt_s (Algorithm section, step (v)).
+ * In: E, e, nHI hold U^n.  Out: they hold U^{n+1}.  nH, src are read only.
+ * On RH_ENEWTON, RH_ELINEAR or RH_ENONFINITE the arrays are restored to
+ * U^n, so the caller may retry with a smaller step.  stats may be NULL. */
+rh_status rh_implicit_step(rh_handle* h, double t_n_s, double dt_s, const double* nH,
+                           const double* src, double* E, double* e, double* nHI,
+                           rh_step_stats* stats);
+
+/* Adjoint of one implicit step (implicit-function theorem at the converged
+ * U^{n+1}).  With f(U^{n+1}; U^n, nH, src) = 0 and lambda^{n+1} = dJ/dU^{n+1}
+ * given in (lE, le, lnHI), solve J_U^T mu = lambda^{n+1} (the transposed
+ * Newton system; after local elimination the same symmetric Schur operator
+ * as the forward step) and return lambda^n = -(df/dU^n)^T mu in (lE, le,
+ * lnHI) (overwritten), and accumulate g_src += -(df/dsrc)^T mu and
+ * g_nH += -(df/dnH)^T mu.  E_n..nHI_n and E_1..nHI_1 are the checkpoints
+ * U^n and U^{n+1} (read only).  le and the e-checkpoints are ignored for
+ * isothermal runs.  stats may be NULL. */
+rh_status rh_adjoint_step(rh_handle* h, double t_n_s, double dt_s, const double* nH,
+                          const double* src, const double* E_n, const double* e_n,
+                          const double* nHI_n, const double* E_1, const double* e_1,
+                          const double* nHI_1, double* lE, double* le, double* lnHI,
+                          double* g_src, double* g_nH, rh_step_stats* stats);
+
+/* Evaluate the residual f(U) of the step from U^n = (E_n, e_n, nHI_n) at
+ * the state U = (E, e, nHI), exactly as rh_implicit_step does (face limiter
+ * from U^n, theta-method radiation residual, local residuals).  Outputs
+ * fE, fe, fn (device, may be NULL to skip; fe unused when isothermal) and
+ * *norm_out (host) = ||f(U)|| in the RMS norm. */
+rh_status rh_residual(rh_handle* h, double t_n_s, double dt_s, const double* nH,
+                      const double* src, const double* E_n, const double* e_n,
+                      const double* nHI_n, const double* E, const double* e,
+                      const double* nHI, double* fE, double* fe, double* fn,
+                      double* norm_out);
+
+/* Solve S x = b with the configured multigrid (defect correction in FP64,
+ * V-cycles in FP32 or FP64 by p->precision), where S is the Schur operator
+ * of the Newton system at U = (E, e, nHI) of the step from U^n: the
+ * modified radiation equation (Algorithm section), with the outer iteration
+ * chosen by p->krylov.  b, x: device fields.
+ * Stops when ||b - S x||_2 <= rel_tol ||b||_2 or after max_it cycles;
+ * *iters and *rel_res (host, may be NULL) report what was reached. */
+rh_status rh_schur_solve(rh_handle* h, double t_n_s, double dt_s, const double* nH,
+                         const double* src, const double* E_n, const double* e_n,
+                         const double* nHI_n, const double* E, const double* e,
+                         const double* nHI, const double* b, double* x, double rel_tol,
+                         int32_t max_it, int32_t* iters, double* rel_res);
+
+/* Derived constants of the handle: out[0] sigma_E (cm^2), out[1] K_Gamma
+ * (cm^2 erg^-1), out[2] K_G (cm^2), out[3] eps_bar (erg, mean photon energy),
+ * out[4] h nu_0 (erg), out[5] cell width h (comoving cm), out[6] number of
+ * multigrid levels, out[7] cells on the coarsest level.  n >= 8. */
+rh_status rh_get_constants(const rh_handle* h, double* out, int32_t n);
+
+/* Expansion factor and Hubble rate at cosmic time t_s (host, pure):
+ * a(t) and H(t) = (da/dt)/a from the Friedmann equation for p. */
+rh_status rh_cosmology_at(const rh_params* p, double t_s, double* a, double* H);
+
+/* Cosmic time at which a(t) = a (host, pure; not for the static case). */
+rh_status rh_cosmic_time(const rh_params* p, double a, double* t_s);
+
+/* Message of the last failed call on h (host string, valid until the next
+ * call on h).  h may be NULL: then the message of the last failed
+ * rh_setup / rh_workspace_bytes on this thread. */
+const char* rh_last_error(const rh_handle* h);
+
+/* Release the handle (not the caller's workspace).  NULL is accepted. */
+void rh_destroy(rh_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RH_H */

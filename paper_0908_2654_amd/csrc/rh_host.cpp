@@ -1,0 +1,961 @@
+// Host side of the C ABI: parameter validation, grey constants, cosmology,
+// workspace carve-up, and the Newton / defect-correction / V-cycle drivers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+
+#include "rh_internal.h"
+
+using namespace rh;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------
+// grey constants of the T_B blackbody above h nu_0 (equation grey_definition)
+// with sigma(nu) = sigma_0 (nu_0/nu)^3; evaluated by series (the oracle
+// uses quadrature of the defining integrals).
+// ---------------------------------------------------------------------------
+double expint_E1(double x) {
+  if (x <= 1.0) {  // power series: -gamma - ln x - sum (-x)^k / (k k!)
+    const double euler = 0.57721566490153286061;
+    double sum = 0.0, term = 1.0;
+    for (int k = 1; k < 200; ++k) {
+      term *= -x / k;
+      double add = term / k;
+      sum += add;
+      if (std::fabs(add) < 1e-18 * std::fabs(sum)) break;
+    }
+    return -euler - std::log(x) - sum;
+  }
+  // continued fraction e^-x / (x+1 - 1/(x+3 - 4/(x+5 - ...))), modified Lentz
+  const double tiny = 1e-300;
+  double b = x + 1.0, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 500; ++i) {
+    double an = -(double)i * i;
+    b += 2.0;
+    d = 1.0 / (an * d + b);
+    c = b + an / c;
+    double del = c * d;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-16) break;
+  }
+  return h * std::exp(-x);
+}
+
+struct Grey {
+  double sigma_E, K_Gamma, K_G, eps_bar, hnu0;
+};
+
+Grey grey_constants(const rh_params& p) {
+  Grey g;
+  g.hnu0 = p.hnu0_eV * kEV;
+  if (p.spectrum == RH_SPEC_MONO) {
+    g.sigma_E = p.sigma0_cm2;
+    g.K_Gamma = p.sigma0_cm2 / g.hnu0;
+    g.K_G = 0.0;
+    g.eps_bar = g.hnu0;
+    return g;
+  }
+  const double kT = kKB * p.T_bb_K;
+  const double x = g.hnu0 / kT;
+  double IE = 0.0, IN = 0.0, IsN = 0.0;
+  for (int k = 1; k < 2000; ++k) {
+    const double ek = std::exp(-k * x);
+    const double kk = k;
+    const double tE = ek * (x * x * x / kk + 3 * x * x / (kk * kk) + 6 * x / (kk * kk * kk) +
+                            6 / (kk * kk * kk * kk));
+    const double tN = ek * (x * x / kk + 2 * x / (kk * kk) + 2 / (kk * kk * kk));
+    const double tS = expint_E1(kk * x);
+    IE += tE;
+    IN += tN;
+    IsN += tS;
+    if (tE < 1e-19 * IE && tS < 1e-19 * IsN) break;
+  }
+  const double x3 = x * x * x;
+  const double IsE = -x3 * std::log1p(-std::exp(-x));
+  IsN *= x3;
+  g.sigma_E = p.sigma0_cm2 * IsE / IE;
+  g.K_Gamma = p.sigma0_cm2 * IsN / (kT * IE);
+  g.K_G = g.sigma_E - g.hnu0 * g.K_Gamma;
+  g.eps_bar = kT * IE / IN;
+  return g;
+}
+
+// ---------------------------------------------------------------------------
+// cosmology (Friedmann equation closed forms)
+// ---------------------------------------------------------------------------
+void cosmo_at(const rh_params& p, double t, double& a, double& H) {
+  const double H0 = p.hubble_h * kH100;
+  if (p.cosmology == RH_COSMO_STATIC) {
+    a = 1.0;
+    H = 0.0;
+  } else if (p.cosmology == RH_COSMO_EDS) {
+    a = std::pow(1.5 * H0 * t, 2.0 / 3.0);
+    H = 2.0 / (3.0 * t);
+  } else {
+    const double s = std::sinh(1.5 * std::sqrt(p.Omega_L) * H0 * t);
+    a = std::cbrt(p.Omega_m / p.Omega_L) * std::pow(s, 2.0 / 3.0);
+    H = H0 * std::sqrt(p.Omega_m / (a * a * a) + p.Omega_L);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// validation and multigrid plan
+// ---------------------------------------------------------------------------
+struct Plan {
+  int nlev;
+  int dims[kMaxLevels][3];
+};
+
+bool plan_levels(const rh_params& p, Plan& pl, std::string& err) {
+  int d[3] = {p.nx, p.ny, p.nz};
+  pl.nlev = 1;
+  pl.dims[0][0] = d[0]; pl.dims[0][1] = d[1]; pl.dims[0][2] = d[2];
+  const long long cap = p.mg_coarse_max;
+  while (pl.nlev < kMaxLevels) {
+    long long cells = (long long)d[0] * d[1] * d[2];
+    if (cells <= cap) break;
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) ok = ok && (d[a] % 2 == 0) && d[a] >= 4;
+    if (!ok) break;
+    for (int a = 0; a < 3; ++a) d[a] /= 2;
+    pl.dims[pl.nlev][0] = d[0]; pl.dims[pl.nlev][1] = d[1]; pl.dims[pl.nlev][2] = d[2];
+    ++pl.nlev;
+  }
+  long long cells = (long long)d[0] * d[1] * d[2];
+  if (cells > kCoarseMaxCells) {
+    err = "grid cannot be coarsened to <= 512 cells (dimensions must stay even while halving)";
+    return false;
+  }
+  return true;
+}
+
+bool validate(const rh_params* p, std::string& err) {
+  if (!p) { err = "params is NULL"; return false; }
+  const int d[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a)
+    if (d[a] < 1) { err = "grid dimensions must be >= 1"; return false; }
+  if ((long long)d[0] * d[1] * d[2] > (1LL << 34)) { err = "grid too large"; return false; }
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] < 0 || p->bc[f] > 2) { err = "unknown boundary condition"; return false; }
+  for (int a = 0; a < 3; ++a) {
+    const bool lo = p->bc[2 * a] == RH_BC_PERIODIC, hi = p->bc[2 * a + 1] == RH_BC_PERIODIC;
+    if (lo != hi) { err = "periodic boundaries must be paired"; return false; }
+    if (lo && d[a] < 3) { err = "periodic dimension needs >= 3 cells"; return false; }
+  }
+  if (!(p->box_comoving_cm > 0) || !std::isfinite(p->box_comoving_cm)) { err = "box must be > 0"; return false; }
+  if (!(p->theta > 0.0 && p->theta <= 1.0)) { err = "theta must lie in (0, 1]"; return false; }
+  if (!(p->gamma > 1.0)) { err = "gamma must be > 1"; return false; }
+  if (p->isothermal && !(p->T_iso_K > 0)) { err = "T_iso must be > 0"; return false; }
+  if (p->spectrum != RH_SPEC_MONO && p->spectrum != RH_SPEC_BLACKBODY) { err = "unknown spectrum"; return false; }
+  if (p->spectrum == RH_SPEC_BLACKBODY && !(p->T_bb_K > 0)) { err = "T_bb must be > 0"; return false; }
+  if (!(p->hnu0_eV > 0) || !(p->sigma0_cm2 >= 0)) { err = "hnu0 > 0 and sigma0 >= 0 required"; return false; }
+  if (p->rates != RH_RATES_CONST && p->rates != RH_RATES_FIT) { err = "unknown rates"; return false; }
+  if (p->rates == RH_RATES_CONST && !(p->alphaB_const >= 0)) { err = "alphaB_const must be >= 0"; return false; }
+  if (p->cosmology < 0 || p->cosmology > 2) { err = "unknown cosmology"; return false; }
+  if (p->cosmology != RH_COSMO_STATIC && !(p->hubble_h > 0)) { err = "hubble_h must be > 0"; return false; }
+  if (p->cosmology == RH_COSMO_EDS && std::fabs(p->Omega_m - 1.0) > 1e-12) { err = "EdS needs Omega_m = 1"; return false; }
+  if (p->cosmology == RH_COSMO_FLAT_LCDM &&
+      (std::fabs(p->Omega_m + p->Omega_L - 1.0) > 1e-12 || !(p->Omega_L > 0) || !(p->Omega_m > 0))) {
+    err = "flat LCDM needs Omega_m + Omega_L = 1, both > 0"; return false;
+  }
+  if (p->precision != RH_PREC_FP64 && p->precision != RH_PREC_MIXED) { err = "unknown precision"; return false; }
+  if (!(p->E_floor > 0)) { err = "E_floor must be > 0"; return false; }
+  if (!(p->newton_tol > 0) || p->newton_max_it < 1 || p->ls_max_cuts < 0) { err = "bad Newton settings"; return false; }
+  if (!(p->lin_forcing > 0) || p->lin_max_it < 1) { err = "bad linear settings"; return false; }
+  if (p->mg_pre < 1 || p->mg_post < 0 || p->mg_pre > 16 || p->mg_post > 16) { err = "mg_pre in [1,16], mg_post in [0,16]"; return false; }
+  if (p->mg_coarse_max < 1 || p->mg_coarse_max > kCoarseMaxCells) { err = "mg_coarse_max in [1, 512]"; return false; }
+  if (p->krylov != 0 && p->krylov != 1) { err = "krylov must be 0 or 1"; return false; }
+  Plan pl;
+  if (!plan_levels(*p, pl, err)) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct StateBuf {
+  double* E;
+  double* e;
+  double* n;
+  double* loc[4];  // BCn, BCe, Bfn, Bfe
+};
+
+struct rh_handle {
+  rh_params p;
+  Plan plan;
+  Grey g;
+  double h, compton;
+  long long N;
+  hipStream_t stream;
+  int device;
+  char* ws;
+  size_t ws_bytes;
+  // fine FP64 fields
+  double *En, *en, *nn, *rhsn, *rS, *diag64, *dEa, *dEb;
+  double *r64, *pa, *pb, *q64, *z64;  // conjugate-gradient vectors
+  double* cf64[3];
+  StateBuf B;
+  double* locA[4];
+  double *part, *redout;
+  // levels
+  LevelK<float> L32[kMaxLevels];
+  LevelK<double> L64[kMaxLevels];
+  double *cA, *cInv;
+  float* cInv32;
+  double* cInv64;
+  double* hred;  // pinned host copy of the reductions
+  hipEvent_t ev0, ev1;
+  std::string err;
+  // statistics of the current call
+  int lin_its, local_its_max;
+  double lin_res_max;
+};
+
+namespace {
+
+size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
+  Carver cv{base};
+  const long long N = (long long)p.nx * p.ny * p.nz;
+  h->En = cv.take<double>(N);
+  h->en = cv.take<double>(N);
+  h->nn = cv.take<double>(N);
+  h->rhsn = cv.take<double>(N);
+  h->rS = cv.take<double>(N);
+  h->diag64 = cv.take<double>(N);
+  h->dEa = cv.take<double>(N);
+  h->dEb = cv.take<double>(N);
+  if (p.krylov) {
+    h->r64 = cv.take<double>(N);
+    h->pa = cv.take<double>(N);
+    h->pb = cv.take<double>(N);
+    h->q64 = cv.take<double>(N);
+    h->z64 = cv.take<double>(N);
+  }
+  for (int d = 0; d < 3; ++d) h->cf64[d] = cv.take<double>(N);
+  h->B.E = cv.take<double>(N);
+  h->B.e = cv.take<double>(N);
+  h->B.n = cv.take<double>(N);
+  for (int q = 0; q < 4; ++q) h->B.loc[q] = cv.take<double>(N);
+  for (int q = 0; q < 4; ++q) h->locA[q] = cv.take<double>(N);
+  h->part = cv.take<double>((size_t)RS_COUNT * kRedBlocks);
+  h->redout = cv.take<double>(RS_COUNT);
+  const bool mixed = p.precision == RH_PREC_MIXED;
+  for (int l = 0; l < pl.nlev; ++l) {
+    const int* d = pl.dims[l];
+    const long long n = (long long)d[0] * d[1] * d[2];
+    const int per[3] = {p.bc[0] == RH_BC_PERIODIC, p.bc[2] == RH_BC_PERIODIC,
+                        p.bc[4] == RH_BC_PERIODIC};
+    if (mixed) {
+      LevelK<float>& L = h->L32[l];
+      L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
+      for (int a = 0; a < 3; ++a) L.per[a] = per[a];
+      L.x = cv.take<float>(n);
+      L.b = cv.take<float>(n);
+      L.r = cv.take<float>(n);
+      L.diag = cv.take<float>(n);
+      for (int a = 0; a < 3; ++a) L.cf[a] = cv.take<float>(n);
+    } else {
+      LevelK<double>& L = h->L64[l];
+      L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
+      for (int a = 0; a < 3; ++a) L.per[a] = per[a];
+      L.x = cv.take<double>(n);
+      L.b = cv.take<double>(n);
+      L.r = cv.take<double>(n);
+      if (l == 0) {
+        L.diag = h->diag64;
+        for (int a = 0; a < 3; ++a) L.cf[a] = h->cf64[a];
+      } else {
+        L.diag = cv.take<double>(n);
+        for (int a = 0; a < 3; ++a) L.cf[a] = cv.take<double>(n);
+      }
+    }
+  }
+  const int* dc = pl.dims[pl.nlev - 1];
+  const long long nc = (long long)dc[0] * dc[1] * dc[2];
+  h->cA = cv.take<double>(nc * nc);
+  h->cInv = cv.take<double>(nc * nc);
+  h->cInv32 = mixed ? cv.take<float>(nc * nc) : nullptr;
+  h->cInv64 = mixed ? nullptr : cv.take<double>(nc * nc);
+  return cv.off + 256;
+}
+
+#define HIPCHK(call)                                                           \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      h->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call; \
+      return RH_EHIP;                                                          \
+    }                                                                          \
+  } while (0)
+
+rh_status fail(rh_handle* h, rh_status st, const std::string& msg) {
+  h->err = msg;
+  return st;
+}
+
+StepK make_step(rh_handle* h, double t_n, double dt) {
+  const rh_params& p = h->p;
+  StepK k;
+  k.nx = p.nx; k.ny = p.ny; k.nz = p.nz;
+  k.N = h->N;
+  for (int f = 0; f < 6; ++f) k.bc[f] = p.bc[f];
+  k.iso = p.isothermal ? 1 : 0;
+  k.rates = p.rates;
+  k.cooling = p.cooling_mask;
+  k.theta_lt1 = p.theta < 1.0 ? 1 : 0;
+  k.h = h->h;
+  k.dt = dt;
+  k.theta = p.theta;
+  cosmo_at(p, t_n, k.a_n, k.H_n);
+  cosmo_at(p, t_n + dt, k.a_1, k.H_1);
+  k.sigma_E = h->g.sigma_E;
+  k.K_Gamma = h->g.K_Gamma;
+  k.K_G = h->g.K_G;
+  k.hnu0 = h->g.hnu0;
+  k.T_iso = p.T_iso_K;
+  k.alphaB = p.alphaB_const;
+  k.gamma = p.gamma;
+  k.compton = h->compton;
+  k.E_floor = p.E_floor;
+  k.R_min = p.R_min > 0 ? p.R_min : 1.0 / (k.a_n * p.box_comoving_cm);
+  k.cf_scale = dt * p.theta / (k.a_1 * k.a_1 * h->h * h->h);
+  k.expl_ratio = (1.0 - p.theta) / p.theta * (k.a_1 * k.a_1) / (k.a_n * k.a_n);
+  k.E_s = 1.0;
+  return k;
+}
+
+rh_status sync_reductions(rh_handle* h, int nslots) {
+  launch_finalize(h->stream, h->part, h->redout, nslots, h->N);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * nslots, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return RH_OK;
+}
+
+double nvars(const rh_handle* h) { return h->p.isothermal ? 2.0 : 3.0; }
+
+// Per-step setup: U^n copies are already in En/en/nn.
+rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
+  const bool mixed = h->p.precision == RH_PREC_MIXED;
+  float* c32[3] = {nullptr, nullptr, nullptr};
+  if (mixed)
+    for (int a = 0; a < 3; ++a) c32[a] = h->L32[0].cf[a];
+  launch_step_setup(h->stream, k, h->En, h->nn, src, h->cf64[0], h->cf64[1], h->cf64[2], c32[0],
+                    c32[1], c32[2], h->rhsn, h->part);
+  HIPCHK(hipGetLastError());
+  rh_status st = sync_reductions(h, RS_COUNT);
+  if (st != RH_OK) return st;
+  if (h->hred[RS_NONFINITE] != 0.0) return fail(h, RH_ENONFINITE, "non-finite E^n, n_HI^n or src");
+  k.E_s = std::max(std::max(h->hred[RS_EMAX], k.dt * h->hred[RS_SMAX]), h->p.E_floor);
+  // coarse face coefficients
+  for (int l = 1; l < h->plan.nlev; ++l) {
+    const int* fd = h->plan.dims[l - 1];
+    if (mixed) {
+      const float* f[3] = {h->L32[l - 1].cf[0], h->L32[l - 1].cf[1], h->L32[l - 1].cf[2]};
+      launch_coarsen_faces<float, float>(h->stream, fd[0], fd[1], fd[2], f, h->L32[l]);
+    } else {
+      const double* f[3] = {h->L64[l - 1].cf[0], h->L64[l - 1].cf[1], h->L64[l - 1].cf[2]};
+      launch_coarsen_faces<double, double>(h->stream, fd[0], fd[1], fd[2], f, h->L64[l]);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  return RH_OK;
+}
+
+struct EvalOut {
+  double norm, rmax;
+  bool finite, local_ok;
+};
+
+// Local solve (mode 0) or evaluation (mode 1) followed by the radiation residual.
+rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const double* dE,
+                     double lam, const StateBuf& out, bool predictor, const double* nH, int mode,
+                     double* fE_out, double* fe_out, double* fn_out, EvalOut& res) {
+  LocalArgs a{};
+  a.Ek = cur.E; a.dE = dE; a.lam = lam;
+  a.ek = cur.e; a.nk = cur.n;
+  if (predictor) {
+    a.pBCn = cur.loc[0]; a.pBCe = cur.loc[1]; a.pBfn = cur.loc[2]; a.pBfe = cur.loc[3];
+  }
+  a.En = h->En; a.en = h->en; a.nn = h->nn; a.nH = nH;
+  a.Et = out.E; a.et = out.e; a.nt = out.n;
+  a.BCn = out.loc[0]; a.BCe = out.loc[1]; a.Bfn = out.loc[2]; a.Bfe = out.loc[3];
+  a.fn_out = fn_out; a.fe_out = fe_out;
+  a.mode = mode;
+  launch_local(h->stream, k, a, h->part);
+  HIPCHK(hipGetLastError());
+  ResidArgs r{};
+  r.E = mode == 0 ? out.E : cur.E;
+  r.n = mode == 0 ? out.n : cur.n;
+  r.En = h->En; r.nn = h->nn;
+  for (int d = 0; d < 3; ++d) r.cf[d] = h->cf64[d];
+  r.rhsn = h->rhsn;
+  r.BCn = out.loc[0]; r.Bfn = out.loc[2];
+  r.rS = h->rS; r.diag64 = h->diag64;
+  r.diag32 = h->p.precision == RH_PREC_MIXED ? h->L32[0].diag : nullptr;
+  r.fE_out = fE_out;
+  launch_residual(h->stream, k, r, h->part);
+  HIPCHK(hipGetLastError());
+  rh_status st = sync_reductions(h, RS_COUNT);
+  if (st != RH_OK) return st;
+  const double* v = h->hred;
+  const double s = v[RS_FE2] + v[RS_FN2] + (h->p.isothermal ? 0.0 : v[RS_FE_LOC2]);
+  res.norm = std::sqrt(s / (h->N * nvars(h)));
+  res.rmax = v[RS_RMAX];
+  res.finite = std::isfinite(res.norm) && v[RS_NONFINITE] == 0.0 && v[RS_BAD_RES] == 0.0 &&
+               std::isfinite(res.rmax);
+  res.local_ok = v[RS_LOCAL_FAIL] == 0.0;
+  h->local_its_max = std::max(h->local_its_max, (int)v[RS_LOCAL_ITS]);
+  return RH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// multigrid
+// ---------------------------------------------------------------------------
+template <class T>
+LevelK<T>* levels(rh_handle* h);
+template <>
+LevelK<float>* levels<float>(rh_handle* h) { return h->L32; }
+template <>
+LevelK<double>* levels<double>(rh_handle* h) { return h->L64; }
+template <class T>
+T* coarse_inverse(rh_handle* h);
+template <>
+float* coarse_inverse<float>(rh_handle* h) { return h->cInv32; }
+template <>
+double* coarse_inverse<double>(rh_handle* h) { return h->cInv64; }
+
+template <class T>
+rh_status coarse_setup(rh_handle* h) {
+  LevelK<T>* L = levels<T>(h);
+  for (int l = 1; l < h->plan.nlev; ++l) launch_coarse_diag<T>(h->stream, L[l - 1], L[l]);
+  launch_coarsest_inverse<T>(h->stream, L[h->plan.nlev - 1], h->cA, h->cInv, coarse_inverse<T>(h));
+  HIPCHK(hipGetLastError());
+  return RH_OK;
+}
+
+template <class T>
+void vcycle(rh_handle* h, int l) {
+  LevelK<T>* L = levels<T>(h);
+  hipStream_t s = h->stream;
+  if (l == h->plan.nlev - 1) {
+    launch_coarsest_solve<T>(s, L[l], coarse_inverse<T>(h));
+    return;
+  }
+  for (int it = 0; it < h->p.mg_pre; ++it) {
+    launch_rbgs<T>(s, L[l], 0, it == 0);
+    launch_rbgs<T>(s, L[l], 1, 0);
+  }
+  launch_mg_residual<T>(s, L[l]);
+  launch_restrict<T>(s, L[l], L[l + 1]);
+  vcycle<T>(h, l + 1);
+  launch_prolong<T>(s, L[l + 1], L[l]);
+  for (int it = 0; it < h->p.mg_post; ++it) {
+    launch_rbgs<T>(s, L[l], 1, 0);
+    launch_rbgs<T>(s, L[l], 0, 0);
+  }
+}
+
+// Defect correction: S dE = rS with V-cycles in T and FP64 residuals.
+// Stops when the weighted norm sqrt(sum (r/E_s)^2 / (N nvars)) <= target_w,
+// or the plain ||r||_2 <= target_2, or on stagnation, or after max_it.
+// On return *dE_final points at the solution.
+template <class T>
+rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
+                       double target_2, int max_it, double** dE_final, int* its_out,
+                       double* w_out, double* l2_out) {
+  LevelK<T>* L = levels<T>(h);
+  rh_status st = coarse_setup<T>(h);
+  if (st != RH_OK) return st;
+  double* dE_in = h->dEa;
+  double* dE_out = h->dEb;
+  *its_out = 0;
+  if (rmax0 == 0.0) {
+    HIPCHK(hipMemsetAsync(dE_in, 0, sizeof(double) * h->N, h->stream));
+    *dE_final = dE_in;
+    *w_out = 0.0;
+    *l2_out = 0.0;
+    return RH_OK;
+  }
+  double sigma_b = rmax0, rmax_cur = rmax0;
+  launch_cast_scale<T>(h->stream, h->N, h->rS, 1.0 / sigma_b, L[0].b);
+  HIPCHK(hipGetLastError());
+  bool first = true;
+  double prev = INFINITY;
+  int slow = 0;
+  double w = INFINITY, l2 = INFINITY;
+  for (int j = 1; j <= max_it; ++j) {
+    vcycle<T>(h, 0);
+    DefectArgs a{};
+    a.rS = h->rS; a.dE_in = dE_in; a.dE_out = dE_out;
+    a.diag64 = h->diag64;
+    for (int d = 0; d < 3; ++d) a.cf[d] = h->cf64[d];
+    a.first = first ? 1 : 0;
+    a.sigma_x = sigma_b;
+    a.inv_sigma_b = 1.0 / rmax_cur;
+    launch_accum_defect<T>(h->stream, k, a, L[0].x, L[0].b, h->part);
+    HIPCHK(hipGetLastError());
+    sigma_b = rmax_cur;
+    st = sync_reductions(h, RS_COUNT);
+    if (st != RH_OK) return st;
+    std::swap(dE_in, dE_out);
+    first = false;
+    *its_out = j;
+    w = std::sqrt(h->hred[RS_FE2] / (h->N * nvars(h)));
+    l2 = std::sqrt(h->hred[RS_R2]);
+    rmax_cur = h->hred[RS_RMAX];
+    if (!std::isfinite(w) || !std::isfinite(l2))
+      return fail(h, RH_ELINEAR, "non-finite linear residual");
+    if (w <= target_w || l2 <= target_2 || rmax_cur == 0.0) break;
+    slow = (w > 0.9 * prev) ? slow + 1 : 0;
+    if (slow >= 3) break;  // stagnated at the rounding floor
+    prev = w;
+  }
+  *dE_final = dE_in;
+  *w_out = w;
+  *l2_out = l2;
+  return RH_OK;
+}
+
+// Flexible preconditioned conjugate gradients on S x = rS in FP64 with one
+// V-cycle in T as the preconditioner (the symmetric V-cycle makes plain CG
+// valid in exact arithmetic; the flexible beta absorbs FP32 rounding).
+template <class T>
+rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w, double target_2,
+                    int max_it, double** x_final, int* its_out, double* w_out, double* l2_out) {
+  LevelK<T>* L = levels<T>(h);
+  rh_status st = coarse_setup<T>(h);
+  if (st != RH_OK) return st;
+  double* x = h->dEa;
+  *its_out = 0;
+  *x_final = x;
+  if (rmax0 == 0.0) {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * h->N, h->stream));
+    *w_out = 0.0;
+    *l2_out = 0.0;
+    return RH_OK;
+  }
+  HIPCHK(hipMemcpyAsync(h->r64, h->rS, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
+  double sigma_b = rmax0;
+  launch_cast_scale<T>(h->stream, h->N, h->r64, 1.0 / sigma_b, L[0].b);
+  vcycle<T>(h, 0);
+  launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->z64, h->part);
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  double rz = h->hred[RS_ZR];
+  double beta = 0.0, rmax_cur = rmax0;
+  double w = INFINITY, l2 = INFINITY;
+  double* p_in = h->pa;
+  double* p_out = h->pb;
+  const double* const cf[3] = {h->cf64[0], h->cf64[1], h->cf64[2]};
+  for (int j = 1; j <= max_it; ++j) {
+    launch_pcg_dir(h->stream, k, h->diag64, cf, h->z64, p_in, p_out, h->q64, beta, j == 1,
+                   h->part);
+    HIPCHK(hipGetLastError());
+    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    const double pq = h->hred[RS_PQ];
+    if (!(pq > 0.0) || !std::isfinite(pq) || !(rz > 0.0)) {
+      if (j == 1) return fail(h, RH_ELINEAR, "conjugate gradients broke down (S or V-cycle not positive)");
+      break;
+    }
+    const double alpha = rz / pq;
+    launch_pcg_update<T>(h->stream, k, alpha, p_out, h->q64, x, h->r64, 1.0 / rmax_cur, L[0].b,
+                         j == 1, h->part);
+    HIPCHK(hipGetLastError());
+    sigma_b = rmax_cur;
+    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    *its_out = j;
+    w = std::sqrt(h->hred[RS_FE2] / (h->N * nvars(h)));
+    l2 = std::sqrt(h->hred[RS_R2]);
+    rmax_cur = h->hred[RS_RMAX];
+    if (!std::isfinite(w) || !std::isfinite(l2))
+      return fail(h, RH_ELINEAR, "non-finite linear residual");
+    if (w <= target_w || l2 <= target_2 || rmax_cur == 0.0) break;
+    vcycle<T>(h, 0);
+    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->z64, h->part);
+    HIPCHK(hipGetLastError());
+    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    const double rz_new = h->hred[RS_ZR];
+    beta = -alpha * h->hred[RS_ZQ] / rz;
+    rz = rz_new;
+    std::swap(p_in, p_out);
+  }
+  *w_out = w;
+  *l2_out = l2;
+  return RH_OK;
+}
+
+rh_status solve_linear(rh_handle* h, const StepK& k, double rmax0, double target_w,
+                       double target_2, int max_it, double** dE_final, int* its, double* w,
+                       double* l2) {
+  const bool mixed = h->p.precision == RH_PREC_MIXED;
+  if (h->p.krylov) {
+    if (mixed) return pcg_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+    return pcg_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+  }
+  if (mixed)
+    return linear_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+  return linear_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+}
+
+rh_status check_ptrs(rh_handle* h, std::initializer_list<const void*> ptrs) {
+  for (const void* q : ptrs) {
+    if (!q) return fail(h, RH_EINVAL, "NULL field pointer");
+    if (reinterpret_cast<uintptr_t>(q) % 8 != 0) return fail(h, RH_EINVAL, "misaligned field pointer");
+  }
+  return RH_OK;
+}
+
+rh_status copy_state(rh_handle* h, double* E, double* e, double* n, const double* Es,
+                     const double* es, const double* ns) {
+  const size_t bytes = sizeof(double) * h->N;
+  HIPCHK(hipMemcpyAsync(E, Es, bytes, hipMemcpyDeviceToDevice, h->stream));
+  if (!h->p.isothermal) HIPCHK(hipMemcpyAsync(e, es, bytes, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(n, ns, bytes, hipMemcpyDeviceToDevice, h->stream));
+  return RH_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void rh_default_params(rh_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 16;
+  for (int f = 0; f < 6; ++f) p->bc[f] = RH_BC_ZEROFLUX;
+  p->box_comoving_cm = 6.6 * 3.0856775814913673e21;
+  p->isothermal = 0;
+  p->T_iso_K = 1.0e4;
+  p->spectrum = RH_SPEC_BLACKBODY;
+  p->T_bb_K = 1.0e5;
+  p->hnu0_eV = 13.6;
+  p->sigma0_cm2 = 6.3e-18;
+  p->rates = RH_RATES_FIT;
+  p->alphaB_const = 2.59e-13;
+  p->cooling_mask = RH_COOL_RECB | RH_COOL_COLLEXC | RH_COOL_COMPTON;
+  p->cosmology = RH_COSMO_STATIC;
+  p->hubble_h = 0.7;
+  p->Omega_m = 1.0;
+  p->Omega_L = 0.0;
+  p->theta = 1.0;
+  p->E_floor = 1.0e-40;
+  p->R_min = 0.0;
+  p->gamma = 5.0 / 3.0;
+  p->newton_tol = 1.0e-8;
+  p->newton_max_it = 30;
+  p->ls_max_cuts = 10;
+  p->lin_forcing = 1.0e-13;
+  p->lin_max_it = 60;
+  p->precision = RH_PREC_FP64;
+  p->mg_pre = 2;
+  p->mg_post = 2;
+  p->mg_coarse_max = 64;
+  p->krylov = 1;
+}
+
+size_t rh_workspace_bytes(const rh_params* p) {
+  std::string err;
+  if (!validate(p, err)) {
+    g_last_error = err;
+    return 0;
+  }
+  Plan pl;
+  plan_levels(*p, pl, err);
+  rh_handle tmp;
+  return layout(&tmp, *p, pl, nullptr);
+}
+
+rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* hip_stream,
+                   rh_handle** out) {
+  std::string err;
+  if (!out) {
+    g_last_error = "out is NULL";
+    return RH_EINVAL;
+  }
+  *out = nullptr;
+  if (!validate(p, err)) {
+    g_last_error = err;
+    return RH_EINVAL;
+  }
+  const size_t need = rh_workspace_bytes(p);
+  if (!workspace || ws_bytes < need) {
+    g_last_error = "workspace missing or smaller than rh_workspace_bytes";
+    return workspace ? RH_ENOMEM : RH_EINVAL;
+  }
+  rh_handle* h = new rh_handle();
+  h->p = *p;
+  plan_levels(*p, h->plan, err);
+  h->g = grey_constants(*p);
+  h->h = p->box_comoving_cm / p->nx;
+  h->compton = 4.0 * kSigmaT * kARad * kKB * std::pow(kTcmb0, 4) / (kME * kC);
+  h->N = (long long)p->nx * p->ny * p->nz;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = reinterpret_cast<char*>(workspace);
+  h->ws_bytes = ws_bytes;
+  char* base = reinterpret_cast<char*>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+  layout(h, *p, h->plan, base);
+  hipError_t e1 = hipGetDevice(&h->device);
+  hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&h->hred), sizeof(double) * RS_COUNT);
+  hipError_t e3 = hipEventCreate(&h->ev0);
+  hipError_t e4 = hipEventCreate(&h->ev1);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    g_last_error = "HIP initialisation failed";
+    delete h;
+    return RH_EHIP;
+  }
+  *out = h;
+  return RH_OK;
+}
+
+rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH, const double* src,
+                           double* E, double* e, double* nHI, rh_step_stats* stats) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, src, E, nHI});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e})) != RH_OK) return st;
+  if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_n))
+    return fail(h, RH_EINVAL, "dt must be > 0 and t finite");
+  if (h->p.cosmology != RH_COSMO_STATIC && !(t_n > 0))
+    return fail(h, RH_EINVAL, "expanding cosmology needs t > 0");
+  h->lin_its = 0;
+  h->local_its_max = 0;
+  h->lin_res_max = 0.0;
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  StepK k = make_step(h, t_n, dt);
+  if ((st = copy_state(h, h->En, h->en, h->nn, E, e, nHI)) != RH_OK) return st;
+  if ((st = setup_step(h, k, src)) != RH_OK) return st;
+
+  StateBuf A{E, iso ? nullptr : e, nHI, {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
+  StateBuf B = h->B;
+  if (iso) B.e = nullptr;
+  StateBuf* cur = &A;
+  StateBuf* oth = &B;
+  EvalOut ev{};
+  int newton_its = 0, cuts = 0;
+  double res0 = 0.0;
+  rh_status result = RH_OK;
+  // local solve at E = E^n
+  st = eval_state(h, k, *cur, nullptr, 0.0, *oth, false, nH, 0, nullptr, nullptr, nullptr, ev);
+  if (st != RH_OK) return st;
+  std::swap(cur, oth);
+  res0 = ev.norm;
+  for (;;) {
+    if (!ev.finite) { result = fail(h, RH_ENONFINITE, "non-finite residual"); break; }
+    if (!ev.local_ok) { result = fail(h, RH_ELINEAR, "local per-cell solve did not converge"); break; }
+    if (ev.norm <= h->p.newton_tol) break;
+    if (newton_its >= h->p.newton_max_it) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "Newton did not converge in %d iterations (||f|| = %.3e)",
+                    newton_its, ev.norm);
+      result = fail(h, RH_ENEWTON, buf);
+      break;
+    }
+    double* dE = nullptr;
+    int its = 0;
+    double w = 0, l2 = 0;
+    st = solve_linear(h, k, ev.rmax, h->p.lin_forcing * ev.norm, 0.0, h->p.lin_max_it, &dE, &its,
+                      &w, &l2);
+    if (st != RH_OK) { result = st; break; }
+    h->lin_its += its;
+    if (ev.norm > 0) h->lin_res_max = std::max(h->lin_res_max, w / ev.norm);
+    ++newton_its;
+    const double f0 = ev.norm;
+    double lam = 1.0;
+    bool accepted = false;
+    for (int c = 0; c <= h->p.ls_max_cuts; ++c) {
+      st = eval_state(h, k, *cur, dE, lam, *oth, true, nH, 0, nullptr, nullptr, nullptr, ev);
+      if (st != RH_OK) return st;
+      if (ev.finite && ev.local_ok && ev.norm <= (1.0 - 1e-4 * lam) * f0) {
+        accepted = true;
+        break;
+      }
+      lam *= 0.5;
+      ++cuts;
+    }
+    if (!accepted) {
+      result = fail(h, RH_ENEWTON, "line search failed");
+      break;
+    }
+    std::swap(cur, oth);
+  }
+  if (result == RH_OK) {
+    if (cur->E != E) {
+      if ((st = copy_state(h, E, e, nHI, cur->E, cur->e, cur->n)) != RH_OK) return st;
+    }
+  } else {
+    if ((st = copy_state(h, E, e, nHI, h->En, h->en, h->nn)) != RH_OK) return st;
+  }
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->newton_its = newton_its;
+    stats->lin_its_total = h->lin_its;
+    stats->ls_cuts = cuts;
+    stats->local_its_max = h->local_its_max;
+    stats->res0 = res0;
+    stats->res_final = ev.norm;
+    stats->lin_res_max = h->lin_res_max;
+    float ms = 0;
+    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    stats->t_ms[0] = ms;
+  }
+  return result;
+}
+
+rh_status rh_residual(rh_handle* h, double t_n, double dt, const double* nH, const double* src,
+                      const double* E_n, const double* e_n, const double* nHI_n, const double* E,
+                      const double* e, const double* nHI, double* fE, double* fe, double* fn,
+                      double* norm_out) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, src, E_n, nHI_n, E, nHI});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e_n, e})) != RH_OK) return st;
+  if (!(dt > 0)) return fail(h, RH_EINVAL, "dt must be > 0");
+  StepK k = make_step(h, t_n, dt);
+  if ((st = copy_state(h, h->En, h->en, h->nn, E_n, e_n, nHI_n)) != RH_OK) return st;
+  if ((st = setup_step(h, k, src)) != RH_OK) return st;
+  StateBuf U{const_cast<double*>(E), iso ? nullptr : const_cast<double*>(e),
+             const_cast<double*>(nHI), {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
+  EvalOut ev{};
+  st = eval_state(h, k, U, nullptr, 0.0, U, false, nH, 1, fE, iso ? nullptr : fe, fn, ev);
+  if (st != RH_OK) return st;
+  if (norm_out) *norm_out = ev.norm;
+  return RH_OK;
+}
+
+rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, const double* src,
+                         const double* E_n, const double* e_n, const double* nHI_n,
+                         const double* E, const double* e, const double* nHI, const double* b,
+                         double* x, double rel_tol, int32_t max_it, int32_t* iters,
+                         double* rel_res) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, src, E_n, nHI_n, E, nHI, b, x});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e_n, e})) != RH_OK) return st;
+  if (!(dt > 0) || !(rel_tol >= 0) || max_it < 1) return fail(h, RH_EINVAL, "bad dt / tol / max_it");
+  StepK k = make_step(h, t_n, dt);
+  if ((st = copy_state(h, h->En, h->en, h->nn, E_n, e_n, nHI_n)) != RH_OK) return st;
+  if ((st = setup_step(h, k, src)) != RH_OK) return st;
+  StateBuf U{const_cast<double*>(E), iso ? nullptr : const_cast<double*>(e),
+             const_cast<double*>(nHI), {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
+  EvalOut ev{};
+  st = eval_state(h, k, U, nullptr, 0.0, U, false, nH, 1, nullptr, nullptr, nullptr, ev);
+  if (st != RH_OK) return st;
+  // right-hand side b replaces the Schur right-hand side; its norms first
+  HIPCHK(hipMemcpyAsync(h->rS, b, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
+  DefectArgs a{};
+  a.rS = h->rS; a.dE_in = nullptr; a.dE_out = h->dEb;
+  a.diag64 = h->diag64;
+  for (int d = 0; d < 3; ++d) a.cf[d] = h->cf64[d];
+  a.first = 1; a.sigma_x = 0.0; a.inv_sigma_b = 0.0;
+  if (h->p.precision == RH_PREC_MIXED)
+    launch_accum_defect<float>(h->stream, k, a, nullptr, h->L32[0].r, h->part);
+  else
+    launch_accum_defect<double>(h->stream, k, a, nullptr, h->L64[0].r, h->part);
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  const double bnorm = std::sqrt(h->hred[RS_R2]);
+  const double bmax = h->hred[RS_RMAX];
+  double* dE = nullptr;
+  int its = 0;
+  double w = 0, l2 = 0;
+  st = solve_linear(h, k, bmax, 0.0, rel_tol * bnorm, max_it, &dE, &its, &w, &l2);
+  if (st != RH_OK) return st;
+  HIPCHK(hipMemcpyAsync(x, dE, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (iters) *iters = its;
+  if (rel_res) *rel_res = bnorm > 0 ? l2 / bnorm : 0.0;
+  return RH_OK;
+}
+
+rh_status rh_adjoint_step(rh_handle* h, double, double, const double*, const double*,
+                          const double*, const double*, const double*, const double*,
+                          const double*, const double*, double*, double*, double*, double*,
+                          double*, rh_step_stats*) {
+  if (!h) return RH_EINVAL;
+  return fail(h, RH_EINVAL, "adjoint step not available in this build");
+}
+
+rh_status rh_get_constants(const rh_handle* h, double* out, int32_t n) {
+  if (!h || !out || n < 8) return RH_EINVAL;
+  out[0] = h->g.sigma_E;
+  out[1] = h->g.K_Gamma;
+  out[2] = h->g.K_G;
+  out[3] = h->g.eps_bar;
+  out[4] = h->g.hnu0;
+  out[5] = h->h;
+  out[6] = h->plan.nlev;
+  const int* d = h->plan.dims[h->plan.nlev - 1];
+  out[7] = (double)d[0] * d[1] * d[2];
+  return RH_OK;
+}
+
+rh_status rh_cosmology_at(const rh_params* p, double t, double* a, double* H) {
+  if (!p || !a || !H) return RH_EINVAL;
+  if (p->cosmology != RH_COSMO_STATIC && !(t > 0)) return RH_EINVAL;
+  cosmo_at(*p, t, *a, *H);
+  return RH_OK;
+}
+
+rh_status rh_cosmic_time(const rh_params* p, double a, double* t) {
+  if (!p || !t || !(a > 0)) return RH_EINVAL;
+  const double H0 = p->hubble_h * kH100;
+  if (p->cosmology == RH_COSMO_EDS) {
+    *t = std::pow(a, 1.5) / (1.5 * H0);
+    return RH_OK;
+  }
+  if (p->cosmology == RH_COSMO_FLAT_LCDM) {
+    *t = 2.0 / (3.0 * std::sqrt(p->Omega_L) * H0) *
+         std::asinh(std::sqrt(p->Omega_L / p->Omega_m) * std::pow(a, 1.5));
+    return RH_OK;
+  }
+  return RH_EINVAL;
+}
+
+const char* rh_last_error(const rh_handle* h) {
+  return h ? h->err.c_str() : g_last_error.c_str();
+}
+
+void rh_destroy(rh_handle* h) {
+  if (!h) return;
+  if (h->hred) (void)hipHostFree(h->hred);
+  (void)hipEventDestroy(h->ev0);
+  (void)hipEventDestroy(h->ev1);
+  delete h;
+}
+
+}  // extern "C"

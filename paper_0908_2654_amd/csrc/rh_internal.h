@@ -1,0 +1,152 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rh.h"
+
+namespace rh {
+
+// Physical constants, CGS (this library's own copy).
+constexpr double kC = 2.99792458e10;       // speed of light, cm/s
+constexpr double kKB = 1.380649e-16;       // Boltzmann, erg/K
+constexpr double kMH = 1.6735575e-24;      // hydrogen atom mass, g
+constexpr double kEV = 1.602176634e-12;    // erg per eV
+constexpr double kSigmaT = 6.6524587321e-25;
+constexpr double kARad = 7.565723e-15;
+constexpr double kME = 9.1093837015e-28;
+constexpr double kTcmb0 = 2.725;
+constexpr double kMpc = 3.0856775814913673e24;
+constexpr double kH100 = 1.0e7 / kMpc;     // 100 km/s/Mpc in 1/s
+
+constexpr int kBlock = 256;                // threads per block of the 1-D kernels
+constexpr int kRedBlocks = 1024;           // fixed grid of the reducing kernels
+constexpr int kMaxLevels = 16;
+constexpr int kCoarseMaxCells = 512;
+
+// Per-step scalars seen by the kernels (passed by value).
+struct StepK {
+  int nx, ny, nz;
+  long long N;
+  int bc[6];
+  int iso, rates, cooling, theta_lt1;
+  double h, dt, theta;
+  double a_n, a_1, H_n, H_1;
+  double sigma_E, K_Gamma, K_G, hnu0;
+  double T_iso, alphaB, gamma, compton;
+  double E_floor, R_min;
+  double cf_scale;      // dt theta / (a_1^2 h^2): face D -> dimensionless coefficient
+  double expl_ratio;    // (1-theta)/theta (a_1/a_n)^2: implicit -> explicit coefficient
+  double E_s;           // norm scale of E
+};
+
+// One multigrid level (T = float or double).
+template <class T>
+struct LevelK {
+  int nx, ny, nz;
+  long long N;
+  int per[3];           // periodic per dimension
+  T* x;                 // correction
+  T* b;                 // right-hand side
+  T* r;                 // residual scratch
+  T* diag;              // diagonal of the Schur operator
+  T* cf[3];             // + face coefficients (dimensionless, 0 on a non-periodic last face)
+};
+
+// Reduction slots (partials laid out [slot][kRedBlocks]).
+enum RedSlot {
+  RS_FE2 = 0,      // sum (f_E/E_s)^2
+  RS_FN2,          // sum (f_n/n_H)^2
+  RS_FE_LOC2,      // sum (f_e/e^n)^2
+  RS_RMAX,         // max |r|
+  RS_LOCAL_FAIL,   // max over cells: 1 if the local solve failed
+  RS_LOCAL_ITS,    // max local iterations
+  RS_R2,           // sum r^2 (plain)
+  RS_EMAX,         // max E^n
+  RS_SMAX,         // max src
+  RS_NONFINITE,    // max over cells: 1 if an input / local output is not finite
+  RS_BAD_RES,      // max over cells: 1 if f_E or the Schur diagonal is not finite
+  RS_PQ,           // sum p.q   (conjugate gradients)
+  RS_ZR,           // sum z.r
+  RS_ZQ,           // sum z.q
+  RS_COUNT
+};
+
+// ---- launchers (rh_kernels.hip) ------------------------------------------
+void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
+                       const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
+                       float* cf32_x, float* cf32_y, float* cf32_z, double* rhsn,
+                       double* part);
+
+// mode 0: solve the local equations at E = E_k + lam dE (dE may be null);
+// mode 1: evaluate at the given (E, e, n) without solving.
+struct LocalArgs {
+  const double* Ek; const double* dE; double lam;
+  const double* ek; const double* nk;                 // initial guess / given state
+  const double* pBCn; const double* pBCe;              // predictor data of U_k (may be null)
+  const double* pBfn; const double* pBfe;
+  const double* En; const double* en; const double* nn; const double* nH;
+  double* Et; double* et; double* nt;                  // outputs (mode 0)
+  double* BCn; double* BCe; double* Bfn; double* Bfe;  // local terms at the result
+  double* fn_out; double* fe_out;                      // optional residual outputs
+  int mode;
+};
+void launch_local(hipStream_t s, const StepK& k, const LocalArgs& a, double* part);
+
+struct ResidArgs {
+  const double* E; const double* n; const double* En; const double* nn;
+  const double* cf[3]; const double* rhsn;
+  const double* BCn; const double* Bfn;
+  double* rS; double* diag64; float* diag32; double* fE_out;
+};
+void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* part);
+
+// Sums / maxima of the partials of a reducing launch over N fine cells.
+void launch_finalize(hipStream_t s, const double* part, double* out, int nslots, long long N);
+
+template <class Tin, class Tout>
+void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],
+                          const LevelK<Tout>& c);
+template <class T>
+void launch_coarse_diag(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
+template <class T>
+void launch_coarsest_inverse(hipStream_t s, const LevelK<T>& c, double* A, double* Inv,
+                             T* InvT);
+template <class T>
+void launch_coarsest_solve(hipStream_t s, const LevelK<T>& c, const T* InvT);
+template <class T>
+void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init);
+template <class T>
+void launch_mg_residual(hipStream_t s, const LevelK<T>& l);
+template <class T>
+void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
+template <class T>
+void launch_prolong(hipStream_t s, const LevelK<T>& c, const LevelK<T>& f);
+template <class T>
+void launch_cast_scale(hipStream_t s, long long N, const double* r, double inv_sigma, T* b);
+
+struct DefectArgs {
+  const double* rS; const double* dE_in; double* dE_out;
+  const double* diag64; const double* cf[3];
+  int first;           // dE_in is zero
+  double sigma_x;      // correction = sigma_x * x
+  double inv_sigma_b;  // b = r * inv_sigma_b
+};
+template <class T>
+void launch_accum_defect(hipStream_t s, const StepK& k, const DefectArgs& a, const T* x, T* b,
+                         double* part);
+
+void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
+                    const double* z, const double* p_in, double* p_out, double* q, double beta,
+                    int first, double* part);
+template <class T>
+void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double* p,
+                       const double* q, double* x, double* r, double inv_sigma, T* b, int first,
+                       double* part);
+template <class T>
+void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
+                        const double* q, double* z, double* part);
+
+}  // namespace rh

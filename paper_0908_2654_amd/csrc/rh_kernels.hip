@@ -1,0 +1,997 @@
+// HIP kernels of the coupled implicit radiation step (gfx950).
+//
+// Layout: every field is float64 (or float32 on the multigrid levels of the
+// mixed path), C order [x][y][z], z fastest.  Face coefficients are stored
+// for the + face of each cell along each axis; the last cell's + face holds
+// the periodic wrap face, or 0 on a non-periodic boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "rh_internal.h"
+
+namespace rh {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ inline void cell_ijk(long long idx, int ny, int nz, int& i, int& j, int& k) {
+  long long jk = idx % ((long long)ny * nz);
+  i = (int)(idx / ((long long)ny * nz));
+  j = (int)(jk / nz);
+  k = (int)(jk % nz);
+}
+
+__device__ inline long long cell_index(int i, int j, int k, int ny, int nz) {
+  return ((long long)i * ny + j) * nz + k;
+}
+
+// Block reductions over 256 threads (4 wavefronts of 64).
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int NV>
+__device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max)[NV],
+                                          const int (&slot)[NV], double* part) {
+  __shared__ double sh[NV][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double v = is_max[q] ? wave_max(vals[q]) : wave_sum(vals[q]);
+    if (lane == 0) sh[q][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double v = sh[q][0];
+      for (int w = 1; w < kBlock / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
+      part[(long long)slot[q] * kRedBlocks + blockIdx.x] = v;
+    }
+  }
+}
+
+inline int red_grid(long long N) {
+  long long g = (N + kBlock - 1) / kBlock;
+  return (int)(g < kRedBlocks ? (g < 1 ? 1 : g) : kRedBlocks);
+}
+
+// ---------------------------------------------------------------------------
+// face limiter (equation limiter, kappa_S = 0)
+// ---------------------------------------------------------------------------
+__device__ inline double limiter_D(const StepK& k, double EL, double ER, double kL, double kR) {
+  double Ebar = fmax(0.5 * (EL + ER), k.E_floor);
+  double R = fmax(fabs(ER - EL) / (k.a_n * k.h * Ebar), k.R_min);
+  double kap = 0.5 * (kL + kR);
+  return kC * (2.0 * kap + R) / (6.0 * kap * kap + 3.0 * kap * R + R * R);
+}
+
+// Sum of the dimensionless coefficients of the outflow boundary faces of a
+// cell (ghost E = E_floor, ghost opacity = the cell's own).
+__device__ inline double outflow_sum(const StepK& k, int i, int j, int kk, double En_P,
+                                     double kap_P) {
+  double s = 0.0;
+  const int c[3] = {i, j, kk};
+  const int n[3] = {k.nx, k.ny, k.nz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] == 0 && k.bc[2 * d] == RH_BC_OUTFLOW)
+      s += k.cf_scale * limiter_D(k, k.E_floor, En_P, kap_P, kap_P);
+    if (c[d] == n[d] - 1 && k.bc[2 * d + 1] == RH_BC_OUTFLOW)
+      s += k.cf_scale * limiter_D(k, En_P, k.E_floor, kap_P, kap_P);
+  }
+  return s;
+}
+
+// Neighbour along axis d in direction s (+1/-1); returns false if none.
+__device__ inline bool neighbour(const int (&c)[3], const int (&n)[3], const int* per, int d,
+                                 int s, int (&q)[3]) {
+  q[0] = c[0]; q[1] = c[1]; q[2] = c[2];
+  int v = c[d] + s;
+  if (v < 0) {
+    if (!per[d]) return false;
+    v += n[d];
+  } else if (v >= n[d]) {
+    if (!per[d]) return false;
+    v -= n[d];
+  }
+  q[d] = v;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// K0: per-step setup: + face coefficients, constant part of f_E, max E^n, max src
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ nn,
+             const double* __restrict__ src, double* __restrict__ cfx, double* __restrict__ cfy,
+             double* __restrict__ cfz, float* __restrict__ c32x, float* __restrict__ c32y,
+             float* __restrict__ c32z, double* __restrict__ rhsn, double* __restrict__ part) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int n[3] = {k.nx, k.ny, k.nz};
+  const double kfac = k.sigma_E / (k.a_n * k.a_n * k.a_n);
+  double emax = 0.0, smax = 0.0, bad = 0.0;
+  double* cfo[3] = {cfx, cfy, cfz};
+  float* c32[3] = {c32x, c32y, c32z};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    const double EP = En[idx];
+    const double kP = kfac * nn[idx];
+    const double sP = src[idx];
+    emax = fmax(emax, EP);
+    smax = fmax(smax, sP);
+    if (!isfinite(EP) || !isfinite(sP) || !isfinite(kP)) bad = 1.0;
+    double Ln = 0.0;  // dt theta L_{n+1} E^n (used for the explicit part)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int q[3];
+      double cfp = 0.0;
+      if (neighbour(c, n, per, d, +1, q)) {
+        long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+        double EQ = En[Q];
+        cfp = k.cf_scale * limiter_D(k, EP, EQ, kP, kfac * nn[Q]);
+        Ln += cfp * (EQ - EP);
+      }
+      cfo[d][idx] = cfp;
+      if (c32[d]) c32[d][idx] = (float)cfp;
+      if (k.theta_lt1 && neighbour(c, n, per, d, -1, q)) {
+        long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+        double EQ = En[Q];
+        Ln += k.cf_scale * limiter_D(k, EQ, EP, kfac * nn[Q], kP) * (EQ - EP);
+      }
+    }
+    double r = EP + k.dt * k.theta * sP;
+    if (k.theta_lt1) {
+      double bs = outflow_sum(k, c[0], c[1], c[2], EP, kP);
+      Ln += bs * (k.E_floor - EP);
+      // dt (1-theta) (L_n E^n - H_n E^n + src - c kappa_n E^n)
+      r += k.expl_ratio * Ln +
+           k.dt * (1.0 - k.theta) * (-k.H_n * EP + sP - kC * kP * EP);
+    }
+    rhsn[idx] = r;
+  }
+  double v[3] = {emax, smax, bad};
+  const int im[3] = {1, 1, 1};
+  const int sl[3] = {RS_EMAX, RS_SMAX, RS_NONFINITE};
+  block_reduce_store<3>(v, im, sl, part);
+}
+
+void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
+                       const double* src, double* cfx, double* cfy, double* cfz, float* c32x,
+                       float* c32y, float* c32z, double* rhsn, double* part) {
+  hipLaunchKernelGGL(k_step_setup, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, En, nn, src, cfx,
+                     cfy, cfz, c32x, c32y, c32z, rhsn, part);
+}
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers over (n, e, E) for the local Jacobian
+// ---------------------------------------------------------------------------
+struct D3 {
+  double v, g[3];
+};
+__device__ inline D3 dconst(double v) { return D3{v, {0.0, 0.0, 0.0}}; }
+__device__ inline D3 dvar(double v, int i) {
+  D3 r{v, {0.0, 0.0, 0.0}};
+  r.g[i] = 1.0;
+  return r;
+}
+__device__ inline D3 operator+(D3 a, D3 b) {
+  return D3{a.v + b.v, {a.g[0] + b.g[0], a.g[1] + b.g[1], a.g[2] + b.g[2]}};
+}
+__device__ inline D3 operator-(D3 a, D3 b) {
+  return D3{a.v - b.v, {a.g[0] - b.g[0], a.g[1] - b.g[1], a.g[2] - b.g[2]}};
+}
+__device__ inline D3 operator*(D3 a, D3 b) {
+  return D3{a.v * b.v, {a.g[0] * b.v + a.v * b.g[0], a.g[1] * b.v + a.v * b.g[1],
+                        a.g[2] * b.v + a.v * b.g[2]}};
+}
+__device__ inline D3 operator/(D3 a, D3 b) {
+  double iv = 1.0 / b.v, q = a.v * iv;
+  return D3{q, {(a.g[0] - q * b.g[0]) * iv, (a.g[1] - q * b.g[1]) * iv,
+                (a.g[2] - q * b.g[2]) * iv}};
+}
+__device__ inline D3 operator+(D3 a, double b) { return D3{a.v + b, {a.g[0], a.g[1], a.g[2]}}; }
+__device__ inline D3 operator+(double b, D3 a) { return a + b; }
+__device__ inline D3 operator-(D3 a, double b) { return D3{a.v - b, {a.g[0], a.g[1], a.g[2]}}; }
+__device__ inline D3 operator-(double b, D3 a) {
+  return D3{b - a.v, {-a.g[0], -a.g[1], -a.g[2]}};
+}
+__device__ inline D3 operator*(D3 a, double b) {
+  return D3{a.v * b, {a.g[0] * b, a.g[1] * b, a.g[2] * b}};
+}
+__device__ inline D3 operator*(double b, D3 a) { return a * b; }
+__device__ inline D3 operator/(D3 a, double b) { return a * (1.0 / b); }
+__device__ inline D3 operator/(double b, D3 a) { return dconst(b) / a; }
+__device__ inline D3 dexp(D3 a) {
+  double ev = exp(a.v);
+  return D3{ev, {a.g[0] * ev, a.g[1] * ev, a.g[2] * ev}};
+}
+__device__ inline D3 dpow(D3 a, double p) {
+  double pv = pow(a.v, p);
+  double dv = p * pv / a.v;
+  return D3{pv, {a.g[0] * dv, a.g[1] * dv, a.g[2] * dv}};
+}
+__device__ inline D3 dsqrt(D3 a) {
+  double sv = sqrt(a.v);
+  double dv = 0.5 / sv;
+  return D3{sv, {a.g[0] * dv, a.g[1] * dv, a.g[2] * dv}};
+}
+__device__ inline D3 dmax0(D3 a) { return a.v >= 0.0 ? a : dconst(0.0); }
+__device__ inline double dexp(double a) { return exp(a); }
+__device__ inline double dpow(double a, double p) { return pow(a, p); }
+__device__ inline double dsqrt(double a) { return sqrt(a); }
+__device__ inline double dmax0(double a) { return fmax(a, 0.0); }
+template <class S>
+__device__ inline S lift(double v);
+template <>
+__device__ inline double lift<double>(double v) { return v; }
+template <>
+__device__ inline D3 lift<D3>(double v) { return dconst(v); }
+
+// Rate fits (Hui & Gnedin 1997 case B; Cen 1992 collisional excitation).
+template <class S>
+__device__ inline S alpha_B_fit(S T) {
+  S lam = 315614.0 / T;
+  S den = 1.0 + dpow(lam / 2.740, 0.407);
+  return 2.753e-14 * dpow(lam, 1.5) / dpow(den, 2.242);
+}
+template <class S>
+__device__ inline S cool_recB(S T) {
+  S lam = 315614.0 / T;
+  S den = 1.0 + dpow(lam / 2.250, 0.376);
+  return 3.435e-30 * T * dpow(lam, 1.970) / dpow(den, 3.720);
+}
+template <class S>
+__device__ inline S cool_collexc(S T) {
+  return 7.5e-19 * dexp(-118348.0 / T) / (1.0 + dsqrt(T / 1.0e5));
+}
+
+// Rates of the local ODEs at a state: dn/dt = A - B n, de/dt = q - 2 H e.
+template <class S>
+__device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, double a, S& A,
+                                   S& B, S& q) {
+  const double a3 = a * a * a;
+  S Epos = dmax0(E);
+  S T;
+  if (k.iso) {
+    T = lift<S>(k.T_iso);
+  } else {
+    S mu = 1.0 / (2.0 - n / nH);  // 1/(1+x), x = 1 - n/n_H
+    T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
+  }
+  S ne = (nH - n) / a3;
+  S alpha = k.rates ? alpha_B_fit(T) : lift<S>(k.alphaB);
+  A = alpha * ne * nH;
+  B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
+  if (k.iso) {
+    q = lift<S>(0.0);
+    return;
+  }
+  S nHI = n / a3;
+  S G = (kC * k.K_G / a3) * nHI * Epos;
+  S Lam = lift<S>(0.0);
+  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB(T) * ne * ne;
+  if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
+  if (k.cooling & RH_COOL_COMPTON) {
+    const double zp1 = 1.0 / a;
+    Lam = Lam + (k.compton * zp1 * zp1 * zp1 * zp1) * (T - kTcmb0 * zp1) * ne;
+  }
+  q = (G - Lam) * (a3 / (kMH * nH));
+}
+
+// theta-method local solutions S_n(U), S_e(U) with explicit parts Rn, qn.
+template <class S>
+__device__ inline void local_S(const StepK& k, S E, S e, S n, double nH, double nn, double en,
+                               double Rn, double qn, S& Sn, S& Se) {
+  S A, B, q;
+  local_rates(k, E, e, n, nH, k.a_1, A, B, q);
+  const double th = k.theta, dt = k.dt;
+  Sn = (nn + dt * th * A + dt * (1.0 - th) * Rn) / (1.0 + (th * dt) * B);
+  if (k.iso) {
+    Se = lift<S>(en);
+  } else {
+    Se = (en + dt * th * q + dt * (1.0 - th) * qn) / (1.0 + 2.0 * th * dt * k.H_1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K1: local solve / evaluation
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_local(StepK k, LocalArgs a, double* __restrict__ part) {
+  double sfn = 0.0, sfe = 0.0, fail = 0.0, itmax = 0.0, bad = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    const double nH = a.nH[idx];
+    const double nn = a.nn[idx];
+    const double en = k.iso ? 0.0 : a.en[idx];
+    double E = a.Ek[idx];
+    double dEv = 0.0;
+    if (a.dE) {
+      dEv = a.dE[idx];
+      E += a.lam * dEv;
+    }
+    double n = a.nk[idx];
+    double e = k.iso ? 0.0 : a.ek[idx];
+    // explicit parts of the theta method
+    double Rn = 0.0, qn = 0.0;
+    if (k.theta_lt1) {
+      double An, Bn, qq;
+      local_rates<double>(k, a.En[idx], en, nn, nH, k.a_n, An, Bn, qq);
+      Rn = An - Bn * nn;
+      qn = k.iso ? 0.0 : qq - 2.0 * k.H_n * en;
+    }
+    int its = 0;
+    if (a.mode == 0) {
+      // predictor from the linearisation at U_k
+      if (a.pBCn && a.dE) {
+        n -= a.pBfn[idx] + a.pBCn[idx] * a.lam * dEv;
+        if (!k.iso) e -= a.pBfe[idx] + a.pBCe[idx] * a.lam * dEv;
+      }
+      n = fmin(fmax(n, 0.0), nH);
+      if (!k.iso) e = fmax(e, 1e-300);
+      bool conv = false;
+      for (its = 1; its <= 80; ++its) {
+        D3 Sn, Se;
+        D3 nd = dvar(n, 0), ed = dvar(e, 1), Ed = dconst(E);
+        local_S<D3>(k, Ed, ed, nd, nH, nn, en, Rn, qn, Sn, Se);
+        const double fn = n - Sn.v;
+        const double b11 = 1.0 - Sn.g[0];
+        double dn, de = 0.0;
+        if (k.iso) {
+          dn = -fn / b11;
+        } else {
+          const double fe = e - Se.v;
+          const double b12 = -Sn.g[1], b21 = -Se.g[0], b22 = 1.0 - Se.g[1];
+          const double det = b11 * b22 - b12 * b21;
+          dn = -(b22 * fn - b12 * fe) / det;
+          de = -(-b21 * fn + b11 * fe) / det;
+        }
+        double lam = 1.0;
+        if (n + dn < 0.0) lam = fmin(lam, 0.9 * n / (-dn));
+        if (n + dn > nH) lam = fmin(lam, 0.9 * (nH - n) / dn);
+        if (!k.iso && e + de <= 0.0) lam = fmin(lam, 0.9 * e / (-de));
+        n += lam * dn;
+        double small = fabs(lam * dn) / nH;
+        if (!k.iso) {
+          e += lam * de;
+          small = fmax(small, fabs(lam * de) / e);
+        }
+        if (!(small == small)) break;  // NaN
+        if (lam == 1.0 && small <= 1e-15) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv) fail = 1.0;
+      itmax = fmax(itmax, (double)its);
+      a.Et[idx] = E;
+      a.nt[idx] = n;
+      if (!k.iso) a.et[idx] = e;
+    }
+    // local residual and Jacobian terms at the (solved or given) state
+    D3 Sn, Se;
+    local_S<D3>(k, dvar(E, 2), dvar(e, 1), dvar(n, 0), nH, nn, en, Rn, qn, Sn, Se);
+    const double fn = n - Sn.v;
+    const double b11 = 1.0 - Sn.g[0];
+    double Bfn, Bcn, Bfe = 0.0, Bce = 0.0, fe = 0.0;
+    if (k.iso) {
+      Bfn = fn / b11;
+      Bcn = -Sn.g[2] / b11;
+    } else {
+      fe = e - Se.v;
+      const double b12 = -Sn.g[1], b21 = -Se.g[0], b22 = 1.0 - Se.g[1];
+      const double c1 = -Sn.g[2], c2 = -Se.g[2];
+      const double idet = 1.0 / (b11 * b22 - b12 * b21);
+      Bfn = (b22 * fn - b12 * fe) * idet;
+      Bfe = (-b21 * fn + b11 * fe) * idet;
+      Bcn = (b22 * c1 - b12 * c2) * idet;
+      Bce = (-b21 * c1 + b11 * c2) * idet;
+      sfe += (fe / en) * (fe / en);
+    }
+    sfn += (fn / nH) * (fn / nH);
+    if (!isfinite(fn) || !isfinite(fe) || !isfinite(E)) bad = 1.0;
+    a.BCn[idx] = Bcn;
+    a.Bfn[idx] = Bfn;
+    if (!k.iso) {
+      a.BCe[idx] = Bce;
+      a.Bfe[idx] = Bfe;
+    }
+    if (a.fn_out) a.fn_out[idx] = fn;
+    if (a.fe_out && !k.iso) a.fe_out[idx] = fe;
+  }
+  double v[5] = {sfn, sfe, fail, itmax, bad};
+  const int im[5] = {0, 0, 1, 1, 1};
+  const int sl[5] = {RS_FN2, RS_FE_LOC2, RS_LOCAL_FAIL, RS_LOCAL_ITS, RS_NONFINITE};
+  block_reduce_store<5>(v, im, sl, part);
+}
+
+void launch_local(hipStream_t s, const StepK& k, const LocalArgs& a, double* part) {
+  hipLaunchKernelGGL(k_local, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a, part);
+}
+
+// ---------------------------------------------------------------------------
+// K2/K3: radiation residual f_E, Schur right-hand side and diagonal
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int nd[3] = {k.nx, k.ny, k.nz};
+  const double a13 = k.a_1 * k.a_1 * k.a_1;
+  const double dth = k.dt * k.theta;
+  const double kfac_n = k.sigma_E / (k.a_n * k.a_n * k.a_n);
+  double sfe = 0.0, rmax = 0.0, bad = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    const double EP = a.E[idx];
+    const double nP = a.n[idx];
+    double LE = 0.0, csum = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int q[3];
+      if (neighbour(c, nd, per, d, +1, q)) {
+        const double cf = a.cf[d][idx];
+        LE += cf * (a.E[cell_index(q[0], q[1], q[2], k.ny, k.nz)] - EP);
+        csum += cf;
+      }
+      if (neighbour(c, nd, per, d, -1, q)) {
+        const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+        const double cf = a.cf[d][Q];
+        LE += cf * (a.E[Q] - EP);
+        csum += cf;
+      }
+    }
+    bool bnd = (c[0] == 0 || c[0] == k.nx - 1 || c[1] == 0 || c[1] == k.ny - 1 || c[2] == 0 ||
+                c[2] == k.nz - 1);
+    double bs = 0.0;
+    if (bnd) bs = outflow_sum(k, c[0], c[1], c[2], a.En[idx], kfac_n * a.nn[idx]);
+    const double absorb = kC * k.sigma_E * nP / a13;
+    const double fE = EP + dth * (k.H_1 + absorb) * EP - LE + bs * (EP - k.E_floor) - a.rhsn[idx];
+    const double JEn = dth * kC * k.sigma_E * EP / a13;
+    const double diag = 1.0 + dth * (k.H_1 + absorb) + csum + bs - JEn * a.BCn[idx];
+    const double rS = -fE + JEn * a.Bfn[idx];
+    if (a.rS) a.rS[idx] = rS;
+    if (a.diag64) a.diag64[idx] = diag;
+    if (a.diag32) a.diag32[idx] = (float)diag;
+    if (a.fE_out) a.fE_out[idx] = fE;
+    sfe += (fE / k.E_s) * (fE / k.E_s);
+    rmax = fmax(rmax, fabs(rS));
+    if (!isfinite(fE) || !isfinite(diag)) bad = 1.0;
+  }
+  double v[3] = {sfe, rmax, bad};
+  const int im[3] = {0, 1, 1};
+  const int sl[3] = {RS_FE2, RS_RMAX, RS_BAD_RES};
+  block_reduce_store<3>(v, im, sl, part);
+}
+
+void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* part) {
+  hipLaunchKernelGGL(k_residual, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a, part);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic second pass of the reductions
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ part,
+                                                     double* __restrict__ out, int nslots,
+                                                     int nblocks) {
+  __shared__ double sh[kBlock / 64];
+  for (int s = 0; s < nslots; ++s) {
+    const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS ||
+                         s == RS_EMAX || s == RS_SMAX || s == RS_NONFINITE ||
+                         s == RS_BAD_RES);
+    double v = is_max ? -INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+      double p = part[(long long)s * kRedBlocks + b];
+      v = is_max ? fmax(v, p) : v + p;
+    }
+    v = is_max ? wave_max(v) : wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = sh[0];
+      for (int w = 1; w < kBlock / 64; ++w) t = is_max ? fmax(t, sh[w]) : t + sh[w];
+      out[s] = t;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_finalize(hipStream_t s, const double* part, double* out, int nslots, long long N) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, part, out, nslots, red_grid(N));
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: coarse operators
+// ---------------------------------------------------------------------------
+template <class Tin, class Tout>
+__global__ void __launch_bounds__(kBlock)
+k_coarsen_faces(int fnx, int fny, int fnz, const Tin* __restrict__ fx, const Tin* __restrict__ fy,
+                const Tin* __restrict__ fz, LevelK<Tout> c) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int I, J, K;
+    cell_ijk(idx, c.ny, c.nz, I, J, K);
+    // + x face of coarse (I,J,K): fine faces between x = 2I+1 and 2I+2
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        sx += (double)fx[cell_index(2 * I + 1, 2 * J + a, 2 * K + b, fny, fnz)];
+        sy += (double)fy[cell_index(2 * I + a, 2 * J + 1, 2 * K + b, fny, fnz)];
+        sz += (double)fz[cell_index(2 * I + a, 2 * J + b, 2 * K + 1, fny, fnz)];
+      }
+    // mean of the 4 fine faces, times 1/4 for the doubled cell width
+    c.cf[0][idx] = (Tout)(0.0625 * sx);
+    c.cf[1][idx] = (Tout)(0.0625 * sy);
+    c.cf[2][idx] = (Tout)(0.0625 * sz);
+  }
+}
+
+template <class Tin, class Tout>
+void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],
+                          const LevelK<Tout>& c) {
+  hipLaunchKernelGGL((k_coarsen_faces<Tin, Tout>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, fnx,
+                     fny, fnz, fcf[0], fcf[1], fcf[2], c);
+}
+
+// Sum of a cell's interior face coefficients (6 faces).
+template <class T>
+__device__ inline double face_sum(const LevelK<T>& l, const int (&c)[3], long long idx) {
+  const int n[3] = {l.nx, l.ny, l.nz};
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int q[3];
+    if (neighbour(c, n, l.per, d, +1, q)) s += (double)l.cf[d][idx];
+    if (neighbour(c, n, l.per, d, -1, q))
+      s += (double)l.cf[d][cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+  }
+  return s;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_coarse_diag(LevelK<T> f, LevelK<T> c) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int C[3];
+    cell_ijk(idx, c.ny, c.nz, C[0], C[1], C[2]);
+    double sh = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 2; ++d) {
+          int F[3] = {2 * C[0] + a, 2 * C[1] + b, 2 * C[2] + d};
+          long long fi = cell_index(F[0], F[1], F[2], f.ny, f.nz);
+          sh += (double)f.diag[fi] - face_sum(f, F, fi);
+        }
+    c.diag[idx] = (T)(0.125 * sh + face_sum(c, C, idx));
+  }
+}
+
+template <class T>
+void launch_coarse_diag(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
+  hipLaunchKernelGGL((k_coarse_diag<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f, c);
+}
+
+// Coarsest level: assemble the dense matrix in FP64 and invert it by
+// Gauss-Jordan elimination (symmetric, diagonally dominant: no pivoting).
+template <class T>
+__global__ void __launch_bounds__(1024) k_coarsest_inverse(LevelK<T> c, double* A, double* Inv,
+                                                           T* InvT) {
+  const int n = (int)c.N;
+  const int nn = n * n;
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    A[t] = 0.0;
+    Inv[t] = (t / n == t % n) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nd[3] = {c.nx, c.ny, c.nz};
+    for (int P = 0; P < n; ++P) {
+      int C[3];
+      cell_ijk(P, c.ny, c.nz, C[0], C[1], C[2]);
+      A[(long long)P * n + P] += (double)c.diag[P];
+      for (int d = 0; d < 3; ++d) {
+        int q[3];
+        if (neighbour(C, nd, c.per, d, +1, q)) {
+          int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
+          A[(long long)P * n + Q] -= (double)c.cf[d][P];
+        }
+        if (neighbour(C, nd, c.per, d, -1, q)) {
+          int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
+          A[(long long)P * n + Q] -= (double)c.cf[d][Q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __shared__ double colk[kCoarseMaxCells];
+  for (int kk = 0; kk < n; ++kk) {
+    const double piv = A[(long long)kk * n + kk];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      A[(long long)kk * n + j] /= piv;
+      Inv[(long long)kk * n + j] /= piv;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = A[(long long)i * n + kk];
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      const int i = t / n, j = t % n;
+      if (i == kk) continue;
+      const double f = colk[i];
+      A[t] -= f * A[(long long)kk * n + j];
+      Inv[t] -= f * Inv[(long long)kk * n + j];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) InvT[t] = (T)Inv[t];
+}
+
+template <class T>
+void launch_coarsest_inverse(hipStream_t s, const LevelK<T>& c, double* A, double* Inv, T* InvT) {
+  hipLaunchKernelGGL((k_coarsest_inverse<T>), dim3(1), dim3(1024), 0, s, c, A, Inv, InvT);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kCoarseMaxCells) k_coarsest_solve(LevelK<T> c, const T* InvT) {
+  __shared__ T bs[kCoarseMaxCells];
+  const int n = (int)c.N;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bs[i] = c.b[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T s = 0;
+    const T* row = InvT + (long long)i * n;
+    for (int j = 0; j < n; ++j) s += row[j] * bs[j];
+    c.x[i] = s;
+  }
+}
+
+template <class T>
+void launch_coarsest_solve(hipStream_t s, const LevelK<T>& c, const T* InvT) {
+  hipLaunchKernelGGL((k_coarsest_solve<T>), dim3(1), dim3(kCoarseMaxCells), 0, s, c, InvT);
+}
+
+// ---------------------------------------------------------------------------
+// multigrid: smoother, residual, transfers
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ inline T offdiag_sum(const LevelK<T>& l, const int (&c)[3], long long idx) {
+  const int n[3] = {l.nx, l.ny, l.nz};
+  T s = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int q[3];
+    if (neighbour(c, n, l.per, d, +1, q))
+      s += l.cf[d][idx] * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+    if (neighbour(c, n, l.per, d, -1, q)) {
+      long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
+      s += l.cf[d][Q] * l.x[Q];
+    }
+  }
+  return s;
+}
+
+// One colour of a red-black Gauss-Seidel sweep (red: i+j+k even).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_rbgs(LevelK<T> l, int color, int zero_init) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < l.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, l.ny, l.nz, c[0], c[1], c[2]);
+    if (((c[0] + c[1] + c[2]) & 1) != color) continue;
+    T s = l.b[idx];
+    if (!zero_init) s += offdiag_sum(l, c, idx);
+    l.x[idx] = s / l.diag[idx];
+  }
+}
+
+template <class T>
+void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init) {
+  long long g = (l.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_rbgs<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0, s, l,
+                     color, zero_init);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_mg_residual(LevelK<T> l) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < l.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, l.ny, l.nz, c[0], c[1], c[2]);
+    l.r[idx] = l.b[idx] - (l.diag[idx] * l.x[idx] - offdiag_sum(l, c, idx));
+  }
+}
+
+template <class T>
+void launch_mg_residual(hipStream_t s, const LevelK<T>& l) {
+  long long g = (l.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_mg_residual<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0,
+                     s, l);
+}
+
+// Fine index along one axis for a restriction / prolongation stencil:
+// mirror at non-periodic walls, wrap when periodic.
+__device__ inline int fold(int v, int n, int per) {
+  if (v < 0) return per ? v + n : -1 - v;
+  if (v >= n) return per ? v - n : 2 * n - 1 - v;
+  return v;
+}
+
+// Full weighting R = P^T / 8: weights (1,3,3,1)/8 per axis over fine 2I-1..2I+2.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_restrict(LevelK<T> f, LevelK<T> c) {
+  const double w[4] = {0.125, 0.375, 0.375, 0.125};
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int I, J, K;
+    cell_ijk(idx, c.ny, c.nz, I, J, K);
+    double s = 0.0;
+    for (int a = 0; a < 4; ++a) {
+      const int i = fold(2 * I - 1 + a, f.nx, f.per[0]);
+      for (int b = 0; b < 4; ++b) {
+        const int j = fold(2 * J - 1 + b, f.ny, f.per[1]);
+        double sz = 0.0;
+        for (int d = 0; d < 4; ++d) {
+          const int kk = fold(2 * K - 1 + d, f.nz, f.per[2]);
+          sz += w[d] * (double)f.r[cell_index(i, j, kk, f.ny, f.nz)];
+        }
+        s += w[a] * w[b] * sz;
+      }
+    }
+    c.b[idx] = (T)s;
+  }
+}
+
+template <class T>
+void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
+  hipLaunchKernelGGL((k_restrict<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f, c);
+}
+
+// Trilinear cell-centred prolongation (weights 3/4, 1/4 per axis), added to x.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_prolong(LevelK<T> c, LevelK<T> f) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < f.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int i, j, k;
+    cell_ijk(idx, f.ny, f.nz, i, j, k);
+    int I[2], J[2], K[2];
+    I[0] = i >> 1; J[0] = j >> 1; K[0] = k >> 1;
+    I[1] = (i & 1) ? I[0] + 1 : I[0] - 1;
+    J[1] = (j & 1) ? J[0] + 1 : J[0] - 1;
+    K[1] = (k & 1) ? K[0] + 1 : K[0] - 1;
+    // walls: mirror (the neighbour is the cell itself); periodic: wrap
+    I[1] = (I[1] < 0 || I[1] >= c.nx) ? (c.per[0] ? (I[1] + c.nx) % c.nx : I[0]) : I[1];
+    J[1] = (J[1] < 0 || J[1] >= c.ny) ? (c.per[1] ? (J[1] + c.ny) % c.ny : J[0]) : J[1];
+    K[1] = (K[1] < 0 || K[1] >= c.nz) ? (c.per[2] ? (K[1] + c.nz) % c.nz : K[0]) : K[1];
+    const double w[2] = {0.75, 0.25};
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 2; ++d)
+          s += w[a] * w[b] * w[d] * (double)c.x[cell_index(I[a], J[b], K[d], c.ny, c.nz)];
+    f.x[idx] = (T)((double)f.x[idx] + s);
+  }
+}
+
+template <class T>
+void launch_prolong(hipStream_t s, const LevelK<T>& c, const LevelK<T>& f) {
+  long long g = (f.N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_prolong<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0, s,
+                     c, f);
+}
+
+// ---------------------------------------------------------------------------
+// defect correction in FP64
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_cast_scale(long long N, const double* __restrict__ r, double inv_sigma, T* __restrict__ b) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+       idx += (long long)blockDim.x * gridDim.x)
+    b[idx] = (T)(r[idx] * inv_sigma);
+}
+
+template <class T>
+void launch_cast_scale(hipStream_t s, long long N, const double* r, double inv_sigma, T* b) {
+  long long g = (N + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL((k_cast_scale<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0,
+                     s, N, r, inv_sigma, b);
+}
+
+// dE_out = dE_in + sigma_x x;  r = rS - S dE_out;  b = r * inv_sigma_b
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_accum_defect(StepK k, DefectArgs a, const T* __restrict__ x, T* __restrict__ b,
+               double* __restrict__ part) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int nd[3] = {k.nx, k.ny, k.nz};
+  double s2w = 0.0, rmax = 0.0, s2 = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    // x may be null (only the norms of rS are wanted)
+    const double dP = (a.first ? 0.0 : a.dE_in[idx]) + (x ? a.sigma_x * (double)x[idx] : 0.0);
+    double off = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int q[3];
+      if (neighbour(c, nd, per, d, +1, q)) {
+        const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+        const double dQ = (a.first ? 0.0 : a.dE_in[Q]) + (x ? a.sigma_x * (double)x[Q] : 0.0);
+        off += a.cf[d][idx] * dQ;
+      }
+      if (neighbour(c, nd, per, d, -1, q)) {
+        const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+        const double dQ = (a.first ? 0.0 : a.dE_in[Q]) + (x ? a.sigma_x * (double)x[Q] : 0.0);
+        off += a.cf[d][Q] * dQ;
+      }
+    }
+    const double r = a.rS[idx] - (a.diag64[idx] * dP - off);
+    a.dE_out[idx] = dP;
+    b[idx] = (T)(r * a.inv_sigma_b);
+    s2w += (r / k.E_s) * (r / k.E_s);
+    s2 += r * r;
+    rmax = fmax(rmax, fabs(r));
+  }
+  double v[3] = {s2w, rmax, s2};
+  const int im[3] = {0, 1, 0};
+  const int sl[3] = {RS_FE2, RS_RMAX, RS_R2};
+  block_reduce_store<3>(v, im, sl, part);
+}
+
+template <class T>
+void launch_accum_defect(hipStream_t s, const StepK& k, const DefectArgs& a, const T* x, T* b,
+                         double* part) {
+  hipLaunchKernelGGL((k_accum_defect<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a, x, b,
+                     part);
+}
+
+// ---------------------------------------------------------------------------
+// flexible preconditioned conjugate gradients in FP64 (V-cycle preconditioner)
+// ---------------------------------------------------------------------------
+// A: p = z + beta p (p = z when first);  q = S p;  partial p.q
+__global__ void __launch_bounds__(kBlock)
+k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ cfx,
+          const double* __restrict__ cfy, const double* __restrict__ cfz,
+          const double* __restrict__ z, const double* __restrict__ p_in, double* __restrict__ p_out,
+          double* __restrict__ q, double beta, int first, double* __restrict__ part) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int nd[3] = {k.nx, k.ny, k.nz};
+  const double* cf[3] = {cfx, cfy, cfz};
+  double pq = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    const double pP = first ? z[idx] : z[idx] + beta * p_in[idx];
+    double off = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int qq[3];
+      if (neighbour(c, nd, per, d, +1, qq)) {
+        const long long Q = cell_index(qq[0], qq[1], qq[2], k.ny, k.nz);
+        off += cf[d][idx] * (first ? z[Q] : z[Q] + beta * p_in[Q]);
+      }
+      if (neighbour(c, nd, per, d, -1, qq)) {
+        const long long Q = cell_index(qq[0], qq[1], qq[2], k.ny, k.nz);
+        off += cf[d][Q] * (first ? z[Q] : z[Q] + beta * p_in[Q]);
+      }
+    }
+    const double qP = diag[idx] * pP - off;
+    p_out[idx] = pP;
+    q[idx] = qP;
+    pq += pP * qP;
+  }
+  double v[1] = {pq};
+  const int im[1] = {0};
+  const int sl[1] = {RS_PQ};
+  block_reduce_store<1>(v, im, sl, part);
+}
+
+void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
+                    const double* z, const double* p_in, double* p_out, double* q, double beta,
+                    int first, double* part) {
+  hipLaunchKernelGGL(k_pcg_dir, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, diag, cf[0], cf[1],
+                     cf[2], z, p_in, p_out, q, beta, first, part);
+}
+
+// B: x += alpha p;  r -= alpha q;  norms of r;  b = r * inv_sigma (preconditioner input)
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_update(StepK k, double alpha, const double* __restrict__ p, const double* __restrict__ q,
+             double* __restrict__ x, double* __restrict__ r, double inv_sigma, T* __restrict__ b,
+             int first, double* __restrict__ part) {
+  double s2w = 0.0, s2 = 0.0, rmax = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    x[idx] = (first ? 0.0 : x[idx]) + alpha * p[idx];
+    const double rv = r[idx] - alpha * q[idx];
+    r[idx] = rv;
+    b[idx] = (T)(rv * inv_sigma);
+    s2w += (rv / k.E_s) * (rv / k.E_s);
+    s2 += rv * rv;
+    rmax = fmax(rmax, fabs(rv));
+  }
+  double v[3] = {s2w, rmax, s2};
+  const int im[3] = {0, 1, 0};
+  const int sl[3] = {RS_FE2, RS_RMAX, RS_R2};
+  block_reduce_store<3>(v, im, sl, part);
+}
+
+template <class T>
+void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double* p,
+                       const double* q, double* x, double* r, double inv_sigma, T* b, int first,
+                       double* part) {
+  hipLaunchKernelGGL((k_pcg_update<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, alpha, p, q,
+                     x, r, inv_sigma, b, first, part);
+}
+
+// C: z = sigma * zT;  partial z.r and z.q (q may be null on the first pass)
+template <class T>
+__global__ void __launch_bounds__(kBlock)
+k_pcg_precond(StepK k, double sigma, const T* __restrict__ zT, const double* __restrict__ r,
+              const double* __restrict__ q, double* __restrict__ z, double* __restrict__ part) {
+  double zr = 0.0, zq = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    const double zv = sigma * (double)zT[idx];
+    z[idx] = zv;
+    zr += zv * r[idx];
+    if (q) zq += zv * q[idx];
+  }
+  double v[2] = {zr, zq};
+  const int im[2] = {0, 0};
+  const int sl[2] = {RS_ZR, RS_ZQ};
+  block_reduce_store<2>(v, im, sl, part);
+}
+
+template <class T>
+void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
+                        const double* q, double* z, double* part) {
+  hipLaunchKernelGGL((k_pcg_precond<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, sigma, zT, r,
+                     q, z, part);
+}
+
+// ---------------------------------------------------------------------------
+// explicit instantiations
+// ---------------------------------------------------------------------------
+#define RH_INST(T)                                                                            \
+  template void launch_coarse_diag<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);       \
+  template void launch_coarsest_inverse<T>(hipStream_t, const LevelK<T>&, double*, double*,   \
+                                           T*);                                               \
+  template void launch_coarsest_solve<T>(hipStream_t, const LevelK<T>&, const T*);            \
+  template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int);                      \
+  template void launch_mg_residual<T>(hipStream_t, const LevelK<T>&);                         \
+  template void launch_restrict<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);          \
+  template void launch_prolong<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);           \
+  template void launch_cast_scale<T>(hipStream_t, long long, const double*, double, T*);      \
+  template void launch_accum_defect<T>(hipStream_t, const StepK&, const DefectArgs&, const T*, \
+                                       T*, double*);                                          \
+  template void launch_pcg_update<T>(hipStream_t, const StepK&, double, const double*,        \
+                                     const double*, double*, double*, double, T*, int,        \
+                                     double*);                                                \
+  template void launch_pcg_precond<T>(hipStream_t, const StepK&, double, const T*,            \
+                                      const double*, const double*, double*, double*);
+RH_INST(float)
+RH_INST(double)
+template void launch_coarsen_faces<double, double>(hipStream_t, int, int, int,
+                                                   const double* const[3], const LevelK<double>&);
+template void launch_coarsen_faces<double, float>(hipStream_t, int, int, int,
+                                                  const double* const[3], const LevelK<float>&);
+template void launch_coarsen_faces<float, float>(hipStream_t, int, int, int,
+                                                 const float* const[3], const LevelK<float>&);
+
+}  // namespace rh

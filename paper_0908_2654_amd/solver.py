@@ -1,0 +1,167 @@
+"""Python front end of librh: a handle bound to one device and stream.
+
+PyTorch provides device memory (the workspace and the fields) and the
+stream; every step of the method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import RhParams, RhStepStats, check, lib
+
+_F64 = ctypes.c_double
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("fields must be torch tensors")
+    if t.device.type != "cuda":
+        raise ValueError("fields must live on the HIP device")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("fields must be contiguous float64")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def params_from_workload(w, **overrides) -> RhParams:
+    """Map a workloads.Workload onto the C parameter struct (no arithmetic)."""
+    p = _lib.default_params()
+    p.nx, p.ny, p.nz = (int(d) for d in w.dims)
+    for i, b in enumerate(w.bc):
+        p.bc[i] = int(b)
+    p.box_comoving_cm = float(w.box_comoving_cm)
+    p.isothermal = int(bool(w.isothermal))
+    p.T_iso_K = float(w.T_iso)
+    p.spectrum = int(w.spectrum)
+    p.T_bb_K = float(w.T_bb)
+    p.hnu0_eV = float(w.hnu0_eV)
+    p.sigma0_cm2 = float(w.sigma0)
+    p.rates = int(w.rates)
+    p.alphaB_const = float(w.alphaB_const)
+    p.cooling_mask = int(w.cooling)
+    p.cosmology = int(w.cosmology)
+    p.hubble_h = float(w.hubble_h)
+    p.Omega_m = float(w.Omega_m)
+    p.Omega_L = float(w.Omega_L)
+    p.theta = float(w.theta)
+    p.newton_tol = float(w.newton_tol)
+    p.precision = int(w.precision)
+    p.mg_pre = int(w.mg_pre)
+    p.mg_post = int(w.mg_post)
+    for k, v in overrides.items():
+        if k == "bc":
+            for i, b in enumerate(v):
+                p.bc[i] = int(b)
+            continue
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(p: RhParams) -> int:
+    n = lib.rh_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        check(_lib.RH_EINVAL)
+    return int(n)
+
+
+def cosmology_at(p: RhParams, t: float):
+    a, H = _F64(), _F64()
+    check(lib.rh_cosmology_at(ctypes.byref(p), float(t), ctypes.byref(a), ctypes.byref(H)))
+    return a.value, H.value
+
+
+def cosmic_time(p: RhParams, a: float) -> float:
+    t = _F64()
+    check(lib.rh_cosmic_time(ctypes.byref(p), float(a), ctypes.byref(t)))
+    return t.value
+
+
+class Solver:
+    """Owns a workspace tensor and a library handle on one device/stream."""
+
+    def __init__(self, params: RhParams, device="cuda", stream=None):
+        self.params = params
+        self.device = torch.device(device)
+        self.ws_bytes = workspace_bytes(params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        st = lib.rh_setup(ctypes.byref(params), ctypes.c_void_p(self.ws.data_ptr()),
+                          self.ws_bytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        check(st)
+        self._h = h
+
+    @property
+    def dims(self):
+        p = self.params
+        return (p.nx, p.ny, p.nz)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.rh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def constants(self) -> dict:
+        out = (_F64 * 8)()
+        check(lib.rh_get_constants(self._h, out, 8), self._h)
+        keys = ["sigma_E", "K_Gamma", "K_G", "eps_bar", "hnu0", "h", "levels", "coarse_cells"]
+        return dict(zip(keys, list(out)))
+
+    def step(self, t, dt, nH, src, E, e, nHI) -> dict:
+        """One implicit step in place on (E, e, nHI); returns the step statistics."""
+        st = RhStepStats()
+        s = lib.rh_implicit_step(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(E),
+                                 _ptr(e), _ptr(nHI), ctypes.byref(st))
+        check(s, self._h)
+        return st.as_dict()
+
+    def residual(self, t, dt, nH, src, Un, U, want_fields=True):
+        """f(U) of the step from U^n: returns (fE, fe, fn, norm)."""
+        En, en, nn = Un
+        E, e, n = U
+        fE = torch.empty_like(E) if want_fields else None
+        fe = torch.empty_like(E) if (want_fields and not self.params.isothermal) else None
+        fn = torch.empty_like(E) if want_fields else None
+        norm = _F64()
+        s = lib.rh_residual(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(En), _ptr(en),
+                            _ptr(nn), _ptr(E), _ptr(e), _ptr(n), _ptr(fE), _ptr(fe), _ptr(fn),
+                            ctypes.byref(norm))
+        check(s, self._h)
+        return fE, fe, fn, norm.value
+
+    def schur_solve(self, t, dt, nH, src, Un, U, b, rel_tol=1e-12, max_it=100):
+        """Solve S x = b with the Schur operator at U; returns (x, iters, rel_res)."""
+        En, en, nn = Un
+        E, e, n = U
+        x = torch.empty_like(b)
+        it = ctypes.c_int32()
+        rr = _F64()
+        s = lib.rh_schur_solve(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(En),
+                               _ptr(en), _ptr(nn), _ptr(E), _ptr(e), _ptr(n), _ptr(b), _ptr(x),
+                               float(rel_tol), int(max_it), ctypes.byref(it), ctypes.byref(rr))
+        check(s, self._h)
+        return x, it.value, rr.value
+
+    def adjoint_step(self, t, dt, nH, src, Un, U1, lam, g_src, g_nH) -> dict:
+        """Adjoint of one step: lam = (lE, le, lnHI) in/out, gradients accumulated."""
+        En, en, nn = Un
+        E1, e1, n1 = U1
+        lE, le, ln = lam
+        st = RhStepStats()
+        s = lib.rh_adjoint_step(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(En),
+                                _ptr(en), _ptr(nn), _ptr(E1), _ptr(e1), _ptr(n1), _ptr(lE),
+                                _ptr(le), _ptr(ln), _ptr(g_src), _ptr(g_nH), ctypes.byref(st))
+        check(s, self._h)
+        return st.as_dict()

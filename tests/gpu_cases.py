@@ -1,0 +1,80 @@
+"""Shared helpers of the GPU parity tests: workload cases, oracle-built
+inputs (both sides get the same arrays, all made by the oracle and the
+seeded generators), GPU and oracle trajectories, error metrics."""
+import numpy as np
+
+import workloads as W
+from oracle import model as OM, newton as ON
+
+# name -> (workload id, dims, Workload field overrides)
+CASES = {
+    "stromgren16": (0, (16, 16, 16), {}),
+    "lognormal_ragged": (2, (24, 20, 36), {}),
+    "eds_cooling16": (1, (16, 16, 16), {}),
+    "outflow_corner": (0, (16, 16, 16), {
+        "bc": (W.BC_ZEROFLUX, W.BC_OUTFLOW) * 3, "sources": "corner"}),
+    "theta06_smalldt": (2, (16, 16, 16), {"theta": 0.6, "dt_Myr": 0.02}),
+}
+
+
+def make_workload(name):
+    cfg, dims, over = CASES[name]
+    w = W.scaled(cfg, dims)
+    for k, v in over.items():
+        setattr(w, k, v)
+    return w
+
+
+def oracle_inputs(w, **poverrides):
+    op = OM.params_from_workload(w, **poverrides)
+    nH = W.density_field(w)
+    src = OM.source_field(op, W.photon_rate_field(w))
+    E, e, n = OM.initial_state(op, nH, w.x0, w.T0, w.E0)
+    t0, dt, ns = OM.schedule(op, w)
+    return op, dict(nH=nH, src=src, E=E, e=e, n=n, t0=t0, dt=dt)
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def gpu_trajectory(w, inp, nsteps, dev="cuda:0", **prm_over):
+    import paper_0908_2654_amd as P
+    prm = P.params_from_workload(w, **prm_over)
+    s = P.Solver(prm, device=dev)
+    nH, src = to_dev(inp["nH"], dev), to_dev(inp["src"], dev)
+    E, e, n = (to_dev(inp[k], dev) for k in ("E", "e", "n"))
+    stats = []
+    for k in range(nsteps):
+        stats.append(s.step(inp["t0"] + k * inp["dt"], inp["dt"], nH, src, E, e, n))
+    out = tuple(x.cpu().numpy() for x in (E, e, n))
+    s.close()
+    return out, stats
+
+
+def oracle_trajectory(op, inp, nsteps, tol):
+    E, e, n = inp["E"], inp["e"], inp["n"]
+    stats = []
+    for k in range(nsteps):
+        st = {}
+        E, e, n = ON.step(op, inp["t0"] + k * inp["dt"], inp["dt"], inp["nH"], inp["src"],
+                          E, e, n, tol=tol, stats=st)
+        stats.append(st)
+    return (E, e, n), stats
+
+
+def errors(g, o, nH, iso, phi_E_rel=1e-20):
+    """Max relative errors with floors: E (phi_E = phi_E_rel max|E|), e (none),
+    x_HII (1e-6); plus the normwise E error."""
+    Eg, eg, ng = g
+    Eo, eo, no = o
+    phi = phi_E_rel * np.max(np.abs(Eo))
+    err = {
+        "E": float(np.max(np.abs(Eg - Eo) / np.maximum(np.abs(Eo), phi))),
+        "E_l2": float(np.linalg.norm(Eg - Eo) / np.linalg.norm(Eo)),
+        "x": float(np.max(np.abs(ng - no) / nH / np.maximum(1.0 - no / nH, 1e-6))),
+    }
+    if not iso:
+        err["e"] = float(np.max(np.abs(eg - eo) / np.abs(eo)))
+    return err

@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Cases span several tiles and ragged sizes, periodic,
+zero-flux and outflow walls, static and expanding backgrounds, isothermal
+and photoheated gas, theta = 1 and theta < 1, FP64 and mixed precision."""
+import numpy as np
+import pytest
+
+from gpu_cases import CASES, errors, gpu_trajectory, make_workload, oracle_inputs, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_grey_constants_match_oracle(hip_device):
+    import paper_0908_2654_amd as P
+    for case in ("stromgren16", "lognormal_ragged"):
+        w = make_workload(case)
+        op, _ = oracle_inputs(w)
+        s = P.Solver(P.params_from_workload(w), device=hip_device)
+        c = s.constants()
+        for k in ("sigma_E", "K_Gamma", "eps_bar", "hnu0"):
+            assert c[k] == pytest.approx(op.grey[k], rel=1e-13), k
+        assert c["K_G"] == pytest.approx(op.grey["K_G"], rel=1e-11, abs=1e-30)
+        assert c["h"] == pytest.approx(op.h, rel=1e-15)
+        s.close()
+
+
+def _perturbed_state(op, inp, seed=0):
+    """U^n = one oracle step from the initial state; U = U^n perturbed."""
+    from oracle import newton as ON
+    E1, e1, n1 = ON.step(op, inp["t0"], inp["dt"], inp["nH"], inp["src"], inp["E"], inp["e"],
+                         inp["n"], tol=1e-10)
+    rng = np.random.default_rng(seed)
+    Ep = E1 * (1 + 0.2 * rng.standard_normal(E1.shape)) + 1e-3 * np.max(E1) * rng.random(E1.shape)
+    npert = np.clip(n1 * (1 + 0.1 * rng.standard_normal(n1.shape)), 0, inp["nH"])
+    ep = e1 * (1 + 0.1 * rng.random(e1.shape))
+    return (E1, e1, n1), (Ep, ep, npert)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_residual_parity(hip_device, case):
+    import paper_0908_2654_amd as P
+    from oracle import model as OM
+    w = make_workload(case)
+    op, inp = oracle_inputs(w)
+    Un, U = _perturbed_state(op, inp)
+    t, dt = inp["t0"] + inp["dt"], inp["dt"]
+    ctx = OM.make_context(op, t, dt, inp["nH"], inp["src"], *Un)
+    fE, fe, fn = OM.residual(op, ctx, U[0], None if op.isothermal else U[1], U[2])
+    nrm = OM.norm(op, ctx, fE, fe, fn)
+    s = P.Solver(P.params_from_workload(w), device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    gE, ge, gn, gnorm = s.residual(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
+                                   tuple(map(d, U)))
+    s.close()
+    gE, gn = gE.cpu().numpy(), gn.cpu().numpy()
+    eE = np.max(np.abs(gE - fE)) / np.max(np.abs(fE))
+    en_ = np.max(np.abs(gn - fn)) / np.max(np.abs(fn))
+    print(f"{case}: fE {eE:.2e} fn {en_:.2e} norm {gnorm:.6e} vs {nrm:.6e}")
+    assert eE < 1e-12 and en_ < 1e-12
+    if not op.isothermal:
+        ge = ge.cpu().numpy()
+        assert np.max(np.abs(ge - fe)) / np.max(np.abs(fe)) < 1e-12
+    assert gnorm == pytest.approx(nrm, rel=1e-12)
+
+
+@pytest.mark.parametrize("krylov", [1, 0])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner"])
+def test_schur_solve_parity(hip_device, case, precision, krylov):
+    import scipy.sparse.linalg as spla
+
+    import paper_0908_2654_amd as P
+    from oracle import model as OM, newton as ON
+    w = make_workload(case)
+    op, inp = oracle_inputs(w)
+    Un, U = _perturbed_state(op, inp, seed=1)
+    # a locally consistent state, as Newton sees it
+    t, dt = inp["t0"] + inp["dt"], inp["dt"]
+    ctx = OM.make_context(op, t, dt, inp["nH"], inp["src"], *Un)
+    n_loc, e_loc = ON.local_solve(op, ctx, U[0], U[2], U[1])
+    e_loc = Un[1] if op.isothermal else e_loc
+    U = (U[0], e_loc, n_loc)
+    ee = None if op.isothermal else U[1]
+    f = OM.residual(op, ctx, U[0], ee, U[2])
+    loc = ON.local_jacobian(op, ctx, U[0], ee, U[2])
+    JEE, JEn = ON.radiation_jacobian(op, ctx, U[0], U[2])
+    S, _, _, _ = ON.schur_operator(op, loc, JEE, JEn, f[1], f[2], f[0])
+    b = np.random.default_rng(3).standard_normal(op.ncells)
+    x_ref = spla.spsolve(S.tocsc(), b)
+    s = P.Solver(P.params_from_workload(w, precision=precision, krylov=krylov),
+                 device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    x, its, rr = s.schur_solve(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
+                               tuple(map(d, U)), d(b.reshape(op.dims)), rel_tol=1e-13,
+                               max_it=300)
+    s.close()
+    x = x.cpu().numpy().ravel()
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    print(f"{case} prec={precision} krylov={krylov}: its={its} relres={rr:.2e} err={err:.2e}")
+    assert rr < 1e-12
+    assert err < 1e-10
+
+
+TRAJ = [("stromgren16", 20), ("lognormal_ragged", 2), ("eds_cooling16", 3),
+        ("outflow_corner", 3), ("theta06_smalldt", 2)]
+
+
+@pytest.mark.parametrize("case,nsteps", TRAJ)
+def test_step_parity_fp64(hip_device, case, nsteps):
+    w = make_workload(case)
+    op, inp = oracle_inputs(w, newton_tol=1e-12)
+    o, ost = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=0)
+    err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
+    print(case, "fp64", err, [s["newton_its"] for s in gst], [s["lin_its_total"] for s in gst])
+    assert err["E"] < 1e-10 and err["x"] < 1e-10
+    if "e" in err:
+        assert err["e"] < 1e-10
+
+
+MIXED = [("stromgren16", 5), ("lognormal_ragged", 2), ("eds_cooling16", 2)]
+
+
+@pytest.mark.parametrize("case,nsteps", MIXED)
+def test_step_parity_mixed(hip_device, case, nsteps):
+    """FP32 V-cycles inside FP64 refinement reach the oracle's FP64 root when
+    Newton is converged as tightly as in the FP64 parity test."""
+    w = make_workload(case)
+    op, inp = oracle_inputs(w, newton_tol=1e-12)
+    o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=1)
+    err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
+    print(case, "mixed", err, [s["newton_its"] for s in gst], [s["lin_its_total"] for s in gst])
+    assert err["E"] < 1e-6 and err["x"] < 1e-6
+    if "e" in err:
+        assert err["e"] < 1e-6
+
+
+@pytest.mark.parametrize("case,nsteps", MIXED)
+def test_step_mixed_at_timed_tolerance(hip_device, case, nsteps):
+    """At the timed Newton tolerance (||f|| <= 1e-8) the mixed path equals the
+    FP64 path (FP64 refinement removes the FP32 error), and both differ from
+    the tightly converged oracle only by the Newton truncation."""
+    w = make_workload(case)
+    op, inp = oracle_inputs(w, newton_tol=1e-12)
+    o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    res, out = {}, {}
+    for prec in (0, 1):
+        g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-8, precision=prec)
+        out[prec] = g
+        res[prec] = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-6)
+        print(case, "timed prec", prec, res[prec], [s["newton_its"] for s in gst],
+              [s["lin_its_total"] for s in gst], [f"{s['res_final']:.1e}" for s in gst])
+    same = errors(out[1], out[0], inp["nH"], op.isothermal, phi_E_rel=1e-6)
+    print(case, "mixed vs fp64", same)
+    assert same["E"] < 1e-6 and same["x"] < 1e-6 and same.get("e", 0.0) < 1e-6
+    assert res[1]["E_l2"] < 1e-5 and res[1]["x"] < 1e-5 and res[1]["E"] < 1e-5
