@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled implicit radiation step on one MI355X.
+
+Metric: Mcell-updates/s per converged implicit step (||f|| <= 1e-8 in the
+RMS norm), FP32-multigrid + FP64-refinement path, with the plain FP64 path
+timed on the same states beside it.  A step is one rh_implicit_step over the
+whole grid (face limiter, Newton iterations with local solves, residuals,
+Schur operator, preconditioned multigrid solves, line search).
+
+Default workload: the 512^3 reionisation-style volume (flat LCDM, z = 9 -> 7
+in 50 steps, lognormal density sigma_ln = 1.5, 4096 lognormal sources).
+Inputs are seeded synthetic fields and are resident in HBM before timing.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per fine cell of one launch of each kernel class
+# (every input field read once, every output written once; halo re-reads
+# and cache effects count zero).  T = 4 (mixed) or 8 (FP64) bytes.
+def algorithmic_bytes_per_cell(kind, T, iso=False):
+    return {
+        # one colour of a red-black sweep: other-colour x, own b and diag,
+        # all three + face arrays (own + faces and the neighbours' - faces),
+        # own x written
+        "rbgs_fine": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
+        "mg_residual_fine": 6 * T + T,
+        "restrict_fine": T + T / 8,
+        "prolong_fine": T / 8 + 2 * T,
+        "pcg_direction": 8 * 8,             # z, p, diag, 3 cf in; p, q out
+        "pcg_update": 6 * 8 + T,            # p, q, x, r in; x, r out; b out
+        "pcg_precond": T + 3 * 8,           # zT, r, q in; z out
+        "residual_schur": 8 * 8 + 2 * 8 + (T if T == 4 else 0),
+        "local_solve": (12 if not iso else 8) * 8 + (7 if not iso else 4) * 8,
+        "step_setup": 3 * 8 + 3 * 8 + (3 * 4 if T == 4 else 0) + 8,
+    }.get(kind)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_path(P, w, prec, inp, state, t_start, dt, steps, timing):
+    import torch
+    prm = P.params_from_workload(w, precision=prec)
+    s = P.Solver(prm, device=inp["nH"].device)
+    E, e, n = (x.clone() for x in state)
+    if timing:
+        s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        stats.append(s.step(t_start + k * dt, dt, inp["nH"], inp["src"], E, e, n))
+        log(f"  prec={prec} step {k}: newton={stats[-1]['newton_its']} "
+            f"vcycles={stats[-1]['lin_its_total']} res={stats[-1]['res_final']:.2e} "
+            f"gpu_ms={stats[-1]['t_ms'][0]:.1f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = s.kernel_timing() if timing else None
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return wall, stats, kt, (E, e, n)
+
+
+def cpu_baseline(w, nH_full, t0, dt, sub=32):
+    """The oracle, as it stands, on a bounded sample: one implicit step of a
+    sub^3 periodic sub-volume cut from the same workload (same cells, same
+    density and sources inside it, same time and step)."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import model as OM, newton as ON
+    ws = W.get(w)
+    ws.dims = (sub, sub, sub)
+    ws.box_comoving_cm = w.box_comoving_cm * sub / w.dims[0]
+    nH = np.ascontiguousarray(nH_full[:sub, :sub, :sub])
+    Qfull = W.photon_rate_field(w)
+    Q = np.ascontiguousarray(Qfull[:sub, :sub, :sub])
+    op = OM.params_from_workload(ws, newton_tol=1e-8)
+    src = OM.source_field(op, Q)
+    E, e, n = OM.initial_state(op, nH, ws.x0, ws.T0, ws.E0)
+    t1 = time.perf_counter()
+    st = {}
+    ON.step(op, t0, dt, nH, src, E, e, n, stats=st)
+    el = time.perf_counter() - t1
+    return {
+        "value": sub ** 3 / el / 1e6,
+        "unit": "Mcell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one implicit step (Newton to ||f|| <= 1e-8, {st['newton_its']} iterations) of a "
+                  f"{sub}^3 sub-volume of the same workload (same density, sources, t and dt), "
+                  f"{el:.1f} s of CPU time, single-threaded NumPy/SciPy",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0908_2654_amd as P
+    import workloads as W
+    from paper_0908_2654_amd.inputs import device_inputs, schedule
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = W.get(args.config)
+    log(f"workload {w.name} dims={w.dims}: generating inputs")
+    tg = time.perf_counter()
+    nH_host = W.density_field(w)
+    prm = P.params_from_workload(w, precision=1)
+    s0 = P.Solver(prm, device=dev)
+    inp = device_inputs(w, s0, nH_host=nH_host)
+    t0, dt, nsteps = schedule(w, prm)
+    log(f"inputs ready in {time.perf_counter() - tg:.1f} s; dt = {dt:.4e} s")
+    state = [inp["E"], inp["e"], inp["nHI"]]
+    for k in range(args.warmup):
+        st = s0.step(t0 + k * dt, dt, inp["nH"], inp["src"], *state)
+        log(f"  warmup step {k}: newton={st['newton_its']} vcycles={st['lin_its_total']}")
+    torch.cuda.synchronize()
+    s0.close()
+    del s0
+    torch.cuda.empty_cache()
+    t_start = t0 + args.warmup * dt
+    N = w.ncells
+
+    wall_m, st_m, kt_m, out_m = run_path(P, w, 1, inp, state, t_start, dt, args.steps, True)
+    ms_m = 1e3 * wall_m / args.steps
+    value = N * args.steps / wall_m / 1e6
+    log(f"mixed: {ms_m:.1f} ms/step, {value:.1f} Mcell-updates/s")
+
+    fp64 = None
+    if not args.no_fp64:
+        wall_d, st_d, _, out_d = run_path(P, w, 0, inp, state, t_start, dt, args.steps, False)
+        fp64 = {"value": N * args.steps / wall_d / 1e6, "ms_per_step": 1e3 * wall_d / args.steps,
+                "newton_its": [s["newton_its"] for s in st_d],
+                "vcycles": [s["lin_its_total"] for s in st_d]}
+        dE = (out_m[0] - out_d[0]).abs().max().item() / out_d[0].abs().max().item()
+        dx = ((out_m[2] - out_d[2]).abs() / inp["nH"]).max().item()
+        fp64["max_diff_vs_mixed"] = {"E_rel_to_max": dE, "x_HII_abs": dx}
+        log(f"fp64: {fp64['ms_per_step']:.1f} ms/step, {fp64['value']:.1f} Mcell-updates/s")
+
+    # roofline of the dominant kernel (largest total time over the timed steps)
+    T = 4
+    best = None
+    for kind, (ms, cnt) in kt_m.items():
+        b = algorithmic_bytes_per_cell(kind, T, w.isothermal)
+        if b is None or cnt == 0:
+            continue
+        if best is None or ms > best[1]:
+            best = (kind, ms, cnt, b)
+    kind, ms, cnt, bpc = best
+    avg_ms = ms / cnt
+    achieved = bpc * N / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_cell": bpc, "avg_launch_ms": round(avg_ms, 4),
+            "launches": cnt}
+    kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1]} for k, v in kt_m.items() if v[1]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(w, nH_host, t_start, dt)
+        log(f"cpu baseline: {cpu['value']:.4f} Mcell-updates/s")
+
+    line = {
+        "metric": "Mcell-updates/s per implicit step at 1e-8 residual: FP32-MG+refine vs FP64",
+        "value": round(value, 2),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_m, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 multigrid / f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.dims), "sources": w.n_sources,
+                   "steps_of_run": f"{args.warmup}..{args.warmup + args.steps - 1} of {nsteps}",
+                   "newton_tol": 1e-8, "lin_forcing": 1e-13, "outer": "PCG, V(2,2) preconditioner",
+                   "newton_its": [s["newton_its"] for s in st_m],
+                   "vcycles": [s["lin_its_total"] for s in st_m]},
+        "fp64_path": fp64,
+        "roofline": roof,
+        "kernels_ms": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

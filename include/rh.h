@@ -119,7 +119,7 @@ void rh_default_params(rh_params* p);
 size_t rh_workspace_bytes(const rh_params* p);
 
 /* Validate p, compute the grey constants (grey_definition, host FP64
- * quadrature), plan the multigrid levels and carve the workspace.
+ * series), plan the multigrid levels and carve the workspace.
  * workspace: device memory of ws_bytes >= rh_workspace_bytes(p), owned by
  * the caller and untouched by it while the handle lives.  hip_stream: a
  * hipStream_t (NULL = default stream).  *out receives the handle. */
@@ -178,6 +178,24 @@ rh_status rh_schur_solve(rh_handle* h, double t_n_s, double dt_s, const double* 
  * out[4] h nu_0 (erg), out[5] cell width h (comoving cm), out[6] number of
  * multigrid levels, out[7] cells on the coarsest level.  n >= 8. */
 rh_status rh_get_constants(const rh_handle* h, double* out, int32_t n);
+
+/* Per-kernel GPU timing for measurement.  When enabled, every kernel launch
+ * of the step is bracketed by a pair of hipEvents recorded on the handle's
+ * stream (a fixed pool created here, read back at the step's own
+ * synchronisation points).  Adds host overhead; off by default. */
+rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
+
+/* Accumulated time (ms) and launch count per kernel class since the last
+ * reset, for classes 0..n-1: 0 step setup (face limiter), 1 local solve,
+ * 2 radiation residual + Schur diagonal, 3 reduction finalize, 4 red-black
+ * Gauss-Seidel colour sweep on the finest level, 5 multigrid residual
+ * (finest), 6 restriction (finest), 7 prolongation (finest), 8 coarse levels
+ * (all work below the finest level), 9 conjugate-gradient direction and
+ * S p, 10 conjugate-gradient update, 11 preconditioner rescale, 12 defect
+ * correction update, 13 right-hand-side cast.  ms / counts are host arrays
+ * (either may be NULL); reset != 0 clears the totals afterwards. */
+rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
+                               int32_t reset);
 
 /* Expansion factor and Hubble rate at cosmic time t_s (host, pure):
  * a(t) and H(t) = (da/dt)/a from the Friedmann equation for p. */

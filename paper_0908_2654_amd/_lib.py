@@ -9,6 +9,10 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librh.so")
 
+KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rbgs_fine",
+                  "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
+                  "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast"]
+
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",
                 5: "RH_ENEWTON", 6: "RH_ELINEAR"}
@@ -69,6 +73,9 @@ SIGNATURES = {
     "rh_get_constants": (_i32, [_vp, ctypes.POINTER(_f64), _i32]),
     "rh_cosmology_at": (_i32, [_PP, _f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "rh_cosmic_time": (_i32, [_PP, _f64, ctypes.POINTER(_f64)]),
+    "rh_set_kernel_timing": (_i32, [_vp, _i32]),
+    "rh_get_kernel_timing": (_i32, [_vp, ctypes.POINTER(_f64), ctypes.POINTER(ctypes.c_int64),
+                                    _i32, _i32]),
     "rh_last_error": (ctypes.c_char_p, [_vp]),
     "rh_destroy": (None, [_vp]),
 }
@@ -76,7 +83,7 @@ SIGNATURES = {
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_0908_2654_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_0908_2654_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

@@ -1,6 +1,7 @@
 """Build librh.so (HIP for gfx950) in the package directory.
 
-Usage: python -m paper_0908_2654_amd.build  (or build() from Python).
+Usage: python paper_0908_2654_amd/build.py  (runs without importing the package,
+which would load the library being rebuilt).
 Each source is compiled to an object under _build/ and linked with hipcc.
 """
 import os

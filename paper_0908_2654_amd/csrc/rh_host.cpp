@@ -205,6 +205,11 @@ struct StateBuf {
   double* loc[4];  // BCn, BCe, Bfn, Bfe
 };
 
+enum KernelKind {
+  KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
+  KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_COUNT
+};
+
 struct rh_handle {
   rh_params p;
   Plan plan;
@@ -230,6 +235,14 @@ struct rh_handle {
   double* cInv64;
   double* hred;  // pinned host copy of the reductions
   hipEvent_t ev0, ev1;
+  // optional per-launch timing (event pairs on the handle's stream)
+  static constexpr int kPool = 2048;
+  bool timing = false;
+  int npool = 0;
+  hipEvent_t eva[kPool], evb[kPool];
+  int pkind[kPool];
+  double kms[KK_COUNT] = {};
+  long long kcount[KK_COUNT] = {};
   std::string err;
   // statistics of the current call
   int lin_its, local_its_max;
@@ -349,12 +362,48 @@ StepK make_step(rh_handle* h, double t_n, double dt) {
   return k;
 }
 
+void flush_timing(rh_handle* h) {
+  for (int i = 0; i < h->npool; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->eva[i], h->evb[i]) == hipSuccess) {
+      h->kms[h->pkind[i]] += ms;
+      h->kcount[h->pkind[i]] += 1;
+    }
+  }
+  h->npool = 0;
+  // a failed query must not surface later through hipGetLastError
+  (void)hipGetLastError();
+}
+
+// Brackets one launch with an event pair when timing is on.
+struct Timed {
+  rh_handle* h;
+  int slot = -1;
+  Timed(rh_handle* hh, int kind) : h(hh) {
+    if (!h->timing) return;
+    if (h->npool == rh_handle::kPool) {
+      (void)hipStreamSynchronize(h->stream);
+      flush_timing(h);
+    }
+    slot = h->npool++;
+    h->pkind[slot] = kind;
+    (void)hipEventRecord(h->eva[slot], h->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(h->evb[slot], h->stream);
+  }
+};
+
 rh_status sync_reductions(rh_handle* h, int nslots) {
-  launch_finalize(h->stream, h->part, h->redout, nslots, h->N);
+  {
+    Timed tm(h, KK_FINALIZE);
+    launch_finalize(h->stream, h->part, h->redout, nslots, h->N);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * nslots, hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->timing) flush_timing(h);
   return RH_OK;
 }
 
@@ -366,8 +415,11 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
   float* c32[3] = {nullptr, nullptr, nullptr};
   if (mixed)
     for (int a = 0; a < 3; ++a) c32[a] = h->L32[0].cf[a];
-  launch_step_setup(h->stream, k, h->En, h->nn, src, h->cf64[0], h->cf64[1], h->cf64[2], c32[0],
-                    c32[1], c32[2], h->rhsn, h->part);
+  {
+    Timed tm0(h, KK_SETUP);
+    launch_step_setup(h->stream, k, h->En, h->nn, src, h->cf64[0], h->cf64[1], h->cf64[2],
+                      c32[0], c32[1], c32[2], h->rhsn, h->part);
+  }
   HIPCHK(hipGetLastError());
   rh_status st = sync_reductions(h, RS_COUNT);
   if (st != RH_OK) return st;
@@ -408,7 +460,10 @@ rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const do
   a.BCn = out.loc[0]; a.BCe = out.loc[1]; a.Bfn = out.loc[2]; a.Bfe = out.loc[3];
   a.fn_out = fn_out; a.fe_out = fe_out;
   a.mode = mode;
-  launch_local(h->stream, k, a, h->part);
+  {
+    Timed tm(h, KK_LOCAL);
+    launch_local(h->stream, k, a, h->part);
+  }
   HIPCHK(hipGetLastError());
   ResidArgs r{};
   r.E = mode == 0 ? out.E : cur.E;
@@ -420,7 +475,10 @@ rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const do
   r.rS = h->rS; r.diag64 = h->diag64;
   r.diag32 = h->p.precision == RH_PREC_MIXED ? h->L32[0].diag : nullptr;
   r.fE_out = fE_out;
-  launch_residual(h->stream, k, r, h->part);
+  {
+    Timed tm(h, KK_RESID);
+    launch_residual(h->stream, k, r, h->part);
+  }
   HIPCHK(hipGetLastError());
   rh_status st = sync_reductions(h, RS_COUNT);
   if (st != RH_OK) return st;
@@ -454,8 +512,12 @@ double* coarse_inverse<double>(rh_handle* h) { return h->cInv64; }
 template <class T>
 rh_status coarse_setup(rh_handle* h) {
   LevelK<T>* L = levels<T>(h);
-  for (int l = 1; l < h->plan.nlev; ++l) launch_coarse_diag<T>(h->stream, L[l - 1], L[l]);
-  launch_coarsest_inverse<T>(h->stream, L[h->plan.nlev - 1], h->cA, h->cInv, coarse_inverse<T>(h));
+  {
+    Timed tm(h, KK_COARSE);
+    for (int l = 1; l < h->plan.nlev; ++l) launch_coarse_diag<T>(h->stream, L[l - 1], L[l]);
+    launch_coarsest_inverse<T>(h->stream, L[h->plan.nlev - 1], h->cA, h->cInv,
+                               coarse_inverse<T>(h));
+  }
   HIPCHK(hipGetLastError());
   return RH_OK;
 }
@@ -465,20 +527,23 @@ void vcycle(rh_handle* h, int l) {
   LevelK<T>* L = levels<T>(h);
   hipStream_t s = h->stream;
   if (l == h->plan.nlev - 1) {
+    Timed tm(h, KK_COARSE);
     launch_coarsest_solve<T>(s, L[l], coarse_inverse<T>(h));
     return;
   }
+  const int kr = l == 0 ? KK_RBGS0 : KK_COARSE;
+  // red first on the way down, black first on the way up: the cycle is symmetric
   for (int it = 0; it < h->p.mg_pre; ++it) {
-    launch_rbgs<T>(s, L[l], 0, it == 0);
-    launch_rbgs<T>(s, L[l], 1, 0);
+    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 0, it == 0, l == 0); }
+    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 1, 0, l == 0); }
   }
-  launch_mg_residual<T>(s, L[l]);
-  launch_restrict<T>(s, L[l], L[l + 1]);
+  { Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE); launch_mg_residual<T>(s, L[l]); }
+  { Timed tm(h, l == 0 ? KK_RESTRICT0 : KK_COARSE); launch_restrict<T>(s, L[l], L[l + 1]); }
   vcycle<T>(h, l + 1);
-  launch_prolong<T>(s, L[l + 1], L[l]);
+  { Timed tm(h, l == 0 ? KK_PROLONG0 : KK_COARSE); launch_prolong<T>(s, L[l + 1], L[l]); }
   for (int it = 0; it < h->p.mg_post; ++it) {
-    launch_rbgs<T>(s, L[l], 1, 0);
-    launch_rbgs<T>(s, L[l], 0, 0);
+    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 1, 0, l == 0); }
+    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 0, 0, l == 0); }
   }
 }
 
@@ -519,7 +584,10 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
     a.first = first ? 1 : 0;
     a.sigma_x = sigma_b;
     a.inv_sigma_b = 1.0 / rmax_cur;
-    launch_accum_defect<T>(h->stream, k, a, L[0].x, L[0].b, h->part);
+    {
+      Timed tm(h, KK_DEFECT);
+      launch_accum_defect<T>(h->stream, k, a, L[0].x, L[0].b, h->part);
+    }
     HIPCHK(hipGetLastError());
     sigma_b = rmax_cur;
     st = sync_reductions(h, RS_COUNT);
@@ -563,9 +631,15 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
   }
   HIPCHK(hipMemcpyAsync(h->r64, h->rS, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
   double sigma_b = rmax0;
-  launch_cast_scale<T>(h->stream, h->N, h->r64, 1.0 / sigma_b, L[0].b);
+  {
+    Timed tm(h, KK_CAST);
+    launch_cast_scale<T>(h->stream, h->N, h->r64, 1.0 / sigma_b, L[0].b);
+  }
   vcycle<T>(h, 0);
-  launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->z64, h->part);
+  {
+    Timed tm(h, KK_PCG_PRE);
+    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->z64, h->part);
+  }
   HIPCHK(hipGetLastError());
   if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
   double rz = h->hred[RS_ZR];
@@ -575,8 +649,11 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
   double* p_out = h->pb;
   const double* const cf[3] = {h->cf64[0], h->cf64[1], h->cf64[2]};
   for (int j = 1; j <= max_it; ++j) {
-    launch_pcg_dir(h->stream, k, h->diag64, cf, h->z64, p_in, p_out, h->q64, beta, j == 1,
-                   h->part);
+    {
+      Timed tm(h, KK_PCG_DIR);
+      launch_pcg_dir(h->stream, k, h->diag64, cf, h->z64, p_in, p_out, h->q64, beta, j == 1,
+                     h->part);
+    }
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
     const double pq = h->hred[RS_PQ];
@@ -585,8 +662,11 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
       break;
     }
     const double alpha = rz / pq;
-    launch_pcg_update<T>(h->stream, k, alpha, p_out, h->q64, x, h->r64, 1.0 / rmax_cur, L[0].b,
-                         j == 1, h->part);
+    {
+      Timed tm(h, KK_PCG_UPD);
+      launch_pcg_update<T>(h->stream, k, alpha, p_out, h->q64, x, h->r64, 1.0 / rmax_cur, L[0].b,
+                           j == 1, h->part);
+    }
     HIPCHK(hipGetLastError());
     sigma_b = rmax_cur;
     if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
@@ -598,7 +678,10 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
       return fail(h, RH_ELINEAR, "non-finite linear residual");
     if (w <= target_w || l2 <= target_2 || rmax_cur == 0.0) break;
     vcycle<T>(h, 0);
-    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->z64, h->part);
+    {
+      Timed tm(h, KK_PCG_PRE);
+      launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->z64, h->part);
+    }
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
     const double rz_new = h->hred[RS_ZR];
@@ -828,7 +911,7 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     stats->res_final = ev.norm;
     stats->lin_res_max = h->lin_res_max;
     float ms = 0;
-    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     stats->t_ms[0] = ms;
   }
   return result;
@@ -910,6 +993,45 @@ rh_status rh_adjoint_step(rh_handle* h, double, double, const double*, const dou
   return fail(h, RH_EINVAL, "adjoint step not available in this build");
 }
 
+rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable) {
+  if (!h) return RH_EINVAL;
+  if (enable && !h->timing) {
+    for (int i = 0; i < rh_handle::kPool; ++i) {
+      if (hipEventCreate(&h->eva[i]) != hipSuccess || hipEventCreate(&h->evb[i]) != hipSuccess)
+        return fail(h, RH_EHIP, "hipEventCreate failed");
+    }
+  }
+  if (!enable && h->timing) {
+    (void)hipStreamSynchronize(h->stream);
+    flush_timing(h);
+    for (int i = 0; i < rh_handle::kPool; ++i) {
+      (void)hipEventDestroy(h->eva[i]);
+      (void)hipEventDestroy(h->evb[i]);
+    }
+  }
+  h->timing = enable != 0;
+  return RH_OK;
+}
+
+rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n, int32_t reset) {
+  if (!h || n < 1) return RH_EINVAL;
+  if (h->timing) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    flush_timing(h);
+  }
+  for (int i = 0; i < n && i < KK_COUNT; ++i) {
+    if (ms) ms[i] = h->kms[i];
+    if (counts) counts[i] = h->kcount[i];
+  }
+  if (reset) {
+    for (int i = 0; i < KK_COUNT; ++i) {
+      h->kms[i] = 0.0;
+      h->kcount[i] = 0;
+    }
+  }
+  return RH_OK;
+}
+
 rh_status rh_get_constants(const rh_handle* h, double* out, int32_t n) {
   if (!h || !out || n < 8) return RH_EINVAL;
   out[0] = h->g.sigma_E;
@@ -952,6 +1074,7 @@ const char* rh_last_error(const rh_handle* h) {
 
 void rh_destroy(rh_handle* h) {
   if (!h) return;
+  if (h->timing) rh_set_kernel_timing(h, 0);
   if (h->hred) (void)hipHostFree(h->hred);
   (void)hipEventDestroy(h->ev0);
   (void)hipEventDestroy(h->ev1);

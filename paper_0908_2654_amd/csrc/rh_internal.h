@@ -117,7 +117,7 @@ void launch_coarsest_inverse(hipStream_t s, const LevelK<T>& c, double* A, doubl
 template <class T>
 void launch_coarsest_solve(hipStream_t s, const LevelK<T>& c, const T* InvT);
 template <class T>
-void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init);
+void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, int fine);
 template <class T>
 void launch_mg_residual(hipStream_t s, const LevelK<T>& l);
 template <class T>

@@ -681,8 +681,9 @@ __device__ inline T offdiag_sum(const LevelK<T>& l, const int (&c)[3], long long
   return s;
 }
 
-// One colour of a red-black Gauss-Seidel sweep (red: i+j+k even).
-template <class T>
+// One colour of a red-black Gauss-Seidel sweep (red: i+j+k even).  FINE
+// only gives the finest-level instantiation its own name for profiling.
+template <class T, int FINE>
 __global__ void __launch_bounds__(kBlock) k_rbgs(LevelK<T> l, int color, int zero_init) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < l.N;
        idx += (long long)blockDim.x * gridDim.x) {
@@ -696,10 +697,13 @@ __global__ void __launch_bounds__(kBlock) k_rbgs(LevelK<T> l, int color, int zer
 }
 
 template <class T>
-void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init) {
+void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, int fine) {
   long long g = (l.N + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_rbgs<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0, s, l,
-                     color, zero_init);
+  const dim3 grid((unsigned)(g < 65536 ? g : 65536));
+  if (fine)
+    hipLaunchKernelGGL((k_rbgs<T, 1>), grid, dim3(kBlock), 0, s, l, color, zero_init);
+  else
+    hipLaunchKernelGGL((k_rbgs<T, 0>), grid, dim3(kBlock), 0, s, l, color, zero_init);
 }
 
 template <class T>
@@ -973,7 +977,7 @@ void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT
   template void launch_coarsest_inverse<T>(hipStream_t, const LevelK<T>&, double*, double*,   \
                                            T*);                                               \
   template void launch_coarsest_solve<T>(hipStream_t, const LevelK<T>&, const T*);            \
-  template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int);                      \
+  template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int, int);                 \
   template void launch_mg_residual<T>(hipStream_t, const LevelK<T>&);                         \
   template void launch_restrict<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);          \
   template void launch_prolong<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);           \

@@ -113,6 +113,17 @@ class Solver:
         except Exception:
             pass
 
+    def set_kernel_timing(self, enable: bool):
+        check(lib.rh_set_kernel_timing(self._h, int(bool(enable))), self._h)
+
+    def kernel_timing(self, reset=True) -> dict:
+        """{class: (total ms, launches)} since the last reset."""
+        n = len(_lib.KERNEL_CLASSES)
+        ms = (_F64 * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(lib.rh_get_kernel_timing(self._h, ms, cnt, n, int(bool(reset))), self._h)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
     def constants(self) -> dict:
         out = (_F64 * 8)()
         check(lib.rh_get_constants(self._h, out, 8), self._h)

@@ -155,3 +155,22 @@ def test_step_mixed_at_timed_tolerance(hip_device, case, nsteps):
     print(case, "mixed vs fp64", same)
     assert same["E"] < 1e-6 and same["x"] < 1e-6 and same.get("e", 0.0) < 1e-6
     assert res[1]["E_l2"] < 1e-5 and res[1]["x"] < 1e-5 and res[1]["E"] < 1e-5
+
+
+def test_kernel_timing_does_not_change_results(hip_device):
+    """The optional per-launch event timing only observes: same results, and
+    every kernel class that ran reports launches."""
+    w = make_workload("lognormal_ragged")
+    op, inp = oracle_inputs(w)
+    g0, _ = gpu_trajectory(w, inp, 1, dev=hip_device, precision=1)
+    import paper_0908_2654_amd as P
+    s = P.Solver(P.params_from_workload(w, precision=1), device=hip_device)
+    s.set_kernel_timing(True)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    E, e, n = d(inp["E"]), d(inp["e"]), d(inp["n"])
+    s.step(inp["t0"], inp["dt"], d(inp["nH"]), d(inp["src"]), E, e, n)
+    kt = s.kernel_timing()
+    s.close()
+    assert np.array_equal(E.cpu().numpy(), g0[0]) and np.array_equal(n.cpu().numpy(), g0[2])
+    for k in ("local_solve", "residual_schur", "rbgs_fine", "pcg_direction"):
+        assert kt[k][1] > 0 and kt[k][0] > 0, (k, kt[k])
