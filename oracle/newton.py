@@ -111,7 +111,10 @@ def stencil_jacobian(p: M.Params, func, x, hstep):
 
 
 def _cstep_h(x, scale):
-    return 1e-20 * (np.abs(x) + scale)
+    """Complex-step size: tiny relative to the value itself (the functions are
+    nonlinear on the scale of the value, e.g. the limiter in E where E is
+    1e-35), with a floor far below the field's scale for zero values."""
+    return 1e-20 * np.maximum(np.abs(x), 1e-30 * np.abs(scale))
 
 
 def local_jacobian(p: M.Params, ctx: M.StepContext, E, e, n, wrt_E=True):

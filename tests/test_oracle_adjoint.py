@@ -92,3 +92,46 @@ def _fd_check(case, nsteps, nrand=3, ntop=3):
                                          ("eds_cooling", 2), ("theta06_outflow", 1)])
 def test_adjoint_gradient_against_central_differences(case, nsteps):
     _fd_check(case, nsteps)
+
+
+CASES["stromgren_dark"] = (0, (12, 12, 12), {})
+
+
+@pytest.mark.parametrize("case", ["stromgren_dark", "theta06_outflow"])
+def test_limiter_jacobian_blocks_against_central_differences(case):
+    """Columns of df_E/dE^n and df_E/dn^n (the lagged limiter, and the
+    explicit part when theta < 1) against central differences with steps
+    relative to each value, in the darkest cells (E^n many decades below its
+    maximum, where the limiter is nonlinear on the scale of E^n itself) and
+    in random cells."""
+    cfg, dims, over = CASES[case]
+    w, p, nH, src, t0, dt = _case(cfg, dims, **over)
+    Un = OM.initial_state(p, nH, w.x0, w.T0, w.E0)
+    Un = ON.step(p, t0, dt, nH, src, *Un, tol=1e-13)
+    U1 = ON.step(p, t0 + dt, dt, nH, src, *Un, tol=1e-13)
+    JU, JUn, _, _ = OA._jacobians(p, t0 + dt, dt, nH, src, Un, U1)
+    N = p.ncells
+    off = N if p.isothermal else 2 * N      # E block of the unknown order (n, [e,] E)
+    JEEn = JUn[off:, off:].tocsc()
+    JEnn = JUn[off:, :N].tocsc()
+
+    def fE(En, nn):
+        c = OM.make_context(p, t0 + dt, dt, nH, src, En, Un[1], nn)
+        return OM.f_E(p, c, U1[0], U1[2]).ravel()
+    if case == "stromgren_dark":
+        assert np.min(Un[0]) < 1e-20 * np.max(Un[0])
+    rng = np.random.default_rng(4)
+    dark = np.argsort(Un[0].ravel())[:12]
+    cols = np.unique(np.concatenate([dark, rng.choice(N, 12, replace=False)]))
+    for j in cols:
+        for k, J in ((0, JEEn), (1, JEnn)):
+            base = [Un[0].copy(), Un[2].copy()]
+            h = 1e-6 * abs(base[k].flat[j])
+            bp = [b.copy() for b in base]
+            bm = [b.copy() for b in base]
+            bp[k].flat[j] += h
+            bm[k].flat[j] -= h
+            col = (fE(*bp) - fE(*bm)) / (2 * h)
+            jc = J[:, j].toarray().ravel()
+            scale = np.max(np.abs(col)) + 1e-300
+            assert np.max(np.abs(jc - col)) <= 1e-3 * scale, (k, j, np.max(np.abs(jc - col)), scale)
