@@ -985,12 +985,70 @@ rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, 
   return RH_OK;
 }
 
-rh_status rh_adjoint_step(rh_handle* h, double, double, const double*, const double*,
-                          const double*, const double*, const double*, const double*,
-                          const double*, const double*, double*, double*, double*, double*,
-                          double*, rh_step_stats*) {
+rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
+                          const double* src, const double* E_n, const double* e_n,
+                          const double* nHI_n, const double* E_1, const double* e_1,
+                          const double* nHI_1, double* lE, double* le, double* lnHI,
+                          double* g_src, double* g_nH, rh_step_stats* stats) {
   if (!h) return RH_EINVAL;
-  return fail(h, RH_EINVAL, "adjoint step not available in this build");
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, src, E_n, nHI_n, E_1, nHI_1, lE, lnHI, g_src, g_nH});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e_n, e_1, le})) != RH_OK) return st;
+  if (!(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_n))
+    return fail(h, RH_EINVAL, "dt must be > 0 and t finite");
+  if (h->p.cosmology != RH_COSMO_STATIC && !(t_n > 0))
+    return fail(h, RH_EINVAL, "expanding cosmology needs t > 0");
+  h->lin_its = 0;
+  h->local_its_max = 0;
+  HIPCHK(hipEventRecord(h->ev0, h->stream));
+  StepK k = make_step(h, t_n, dt);
+  // recompute the step's face limiter from U^n and the local terms and the
+  // Schur operator at the converged U^{n+1}
+  if ((st = copy_state(h, h->En, h->en, h->nn, E_n, e_n, nHI_n)) != RH_OK) return st;
+  if ((st = setup_step(h, k, src)) != RH_OK) return st;
+  StateBuf U{const_cast<double*>(E_1), iso ? nullptr : const_cast<double*>(e_1),
+             const_cast<double*>(nHI_1), {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
+  EvalOut ev{};
+  st = eval_state(h, k, U, nullptr, 0.0, U, false, nH, 1, nullptr, nullptr, nullptr, ev);
+  if (st != RH_OK) return st;
+  if (!ev.finite) return fail(h, RH_ENONFINITE, "non-finite state in the adjoint step");
+  // S mu_E = lE - (B^-1 C)^T lambda_loc
+  launch_adj_rhs(h->stream, k, lE, le, lnHI, h->locA[0], h->locA[1], h->rS, h->part);
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  const double rnorm = std::sqrt(h->hred[RS_R2]);
+  const double rmax = h->hred[RS_RMAX];
+  if (!std::isfinite(rnorm)) return fail(h, RH_ENONFINITE, "non-finite adjoint right-hand side");
+  double* mu = nullptr;
+  int its = 0;
+  double w = 0, l2 = 0;
+  st = solve_linear(h, k, rmax, 0.0, 1e-13 * rnorm, h->p.lin_max_it, &mu, &its, &w, &l2);
+  if (st != RH_OK) return st;
+  h->lin_its = its;
+  AdjArgs a{};
+  a.E1 = E_1; a.e1 = iso ? nullptr : e_1; a.n1 = nHI_1;
+  a.En = h->En; a.en = h->en; a.nn = h->nn;
+  a.nH = nH; a.muE = mu;
+  a.lE = lE; a.le = iso ? nullptr : le; a.ln = lnHI;
+  a.g_src = g_src; a.g_nH = g_nH;
+  launch_adj_local(h->stream, k, a);
+  HIPCHK(hipGetLastError());
+  launch_adj_limiter(h->stream, k, a);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->lin_its_total = its;
+    stats->res0 = rnorm;
+    stats->res_final = l2;
+    stats->lin_res_max = rnorm > 0 ? l2 / rnorm : 0.0;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    stats->t_ms[0] = ms;
+  }
+  return RH_OK;
 }
 
 rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable) {

@@ -149,4 +149,18 @@ template <class T>
 void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
                         const double* q, double* z, double* part);
 
+// adjoint step
+struct AdjArgs {
+  const double* E1; const double* e1; const double* n1;   // U^{n+1}
+  const double* En; const double* en; const double* nn;   // U^n
+  const double* nH; const double* muE;                     // mu_E of the Schur solve
+  double* lE; double* le; double* ln;                      // in: lambda^{n+1}; out: lambda^n
+  double* g_src; double* g_nH;                             // accumulated
+};
+void launch_adj_rhs(hipStream_t s, const StepK& k, const double* lE, const double* le,
+                    const double* ln, const double* BCn, const double* BCe, double* r,
+                    double* part);
+void launch_adj_local(hipStream_t s, const StepK& k, const AdjArgs& a);
+void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a);
+
 }  // namespace rh

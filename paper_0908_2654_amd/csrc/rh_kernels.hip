@@ -970,6 +970,270 @@ void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT
 }
 
 // ---------------------------------------------------------------------------
+// adjoint of the step (implicit-function theorem at the converged U^{n+1})
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers with NV derivative slots.
+template <int NV>
+struct DN {
+  double v, g[NV];
+};
+template <int NV>
+__device__ inline DN<NV> dn_const(double v) {
+  DN<NV> r;
+  r.v = v;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = 0.0;
+  return r;
+}
+template <int NV>
+__device__ inline DN<NV> dn_var(double v, int slot) {
+  DN<NV> r = dn_const<NV>(v);
+  r.g[slot] = 1.0;
+  return r;
+}
+#define RH_DN_BIN(OP, VAL, GRAD)                                                   \
+  template <int NV>                                                                \
+  __device__ inline DN<NV> operator OP(DN<NV> a, DN<NV> b) {                       \
+    DN<NV> r;                                                                      \
+    r.v = VAL;                                                                     \
+    _Pragma("unroll") for (int i = 0; i < NV; ++i) r.g[i] = GRAD;                  \
+    return r;                                                                      \
+  }
+RH_DN_BIN(+, a.v + b.v, a.g[i] + b.g[i])
+RH_DN_BIN(-, a.v - b.v, a.g[i] - b.g[i])
+RH_DN_BIN(*, a.v * b.v, a.g[i] * b.v + a.v * b.g[i])
+#undef RH_DN_BIN
+template <int NV>
+__device__ inline DN<NV> operator/(DN<NV> a, DN<NV> b) {
+  const double iv = 1.0 / b.v, q = a.v * iv;
+  DN<NV> r;
+  r.v = q;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = (a.g[i] - q * b.g[i]) * iv;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> operator+(DN<NV> a, double b) { return a + dn_const<NV>(b); }
+template <int NV> __device__ inline DN<NV> operator+(double b, DN<NV> a) { return dn_const<NV>(b) + a; }
+template <int NV> __device__ inline DN<NV> operator-(DN<NV> a, double b) { return a - dn_const<NV>(b); }
+template <int NV> __device__ inline DN<NV> operator-(double b, DN<NV> a) { return dn_const<NV>(b) - a; }
+template <int NV>
+__device__ inline DN<NV> operator*(DN<NV> a, double b) {
+  DN<NV> r;
+  r.v = a.v * b;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * b;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> operator*(double b, DN<NV> a) { return a * b; }
+template <int NV> __device__ inline DN<NV> operator/(DN<NV> a, double b) { return a * (1.0 / b); }
+template <int NV> __device__ inline DN<NV> operator/(double b, DN<NV> a) { return dn_const<NV>(b) / a; }
+template <int NV>
+__device__ inline DN<NV> chain(DN<NV> a, double fv, double dfv) {
+  DN<NV> r;
+  r.v = fv;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * dfv;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> dexp(DN<NV> a) { const double e = exp(a.v); return chain(a, e, e); }
+template <int NV> __device__ inline DN<NV> dpow(DN<NV> a, double p) { const double pv = pow(a.v, p); return chain(a, pv, p * pv / a.v); }
+template <int NV> __device__ inline DN<NV> dsqrt(DN<NV> a) { const double s = sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int NV> __device__ inline DN<NV> dmax0(DN<NV> a) { return a.v >= 0.0 ? a : dn_const<NV>(0.0); }
+template <int NV> __device__ inline DN<NV> dfabs(DN<NV> a) { return a.v < 0.0 ? dn_const<NV>(0.0) - a : a; }
+template <int NV> __device__ inline DN<NV> dfmax(DN<NV> a, double c) { return a.v >= c ? a : dn_const<NV>(c); }
+template <>
+__device__ inline DN<7> lift<DN<7>>(double v) { return dn_const<7>(v); }
+
+// Local rates with the hydrogen density as an independent variable.
+template <class S>
+__device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, double a, S& A, S& B,
+                                      S& q) {
+  const double a3 = a * a * a;
+  S Epos = dmax0(E);
+  S T;
+  if (k.iso) {
+    T = lift<S>(k.T_iso);
+  } else {
+    S mu = 1.0 / (2.0 - n / nH);
+    T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
+  }
+  S ne = (nH - n) / a3;
+  S alpha = k.rates ? alpha_B_fit(T) : lift<S>(k.alphaB);
+  A = alpha * ne * nH;
+  B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
+  if (k.iso) {
+    q = lift<S>(0.0);
+    return;
+  }
+  S nHI = n / a3;
+  S G = (kC * k.K_G / a3) * nHI * Epos;
+  S Lam = lift<S>(0.0);
+  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB(T) * ne * ne;
+  if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
+  if (k.cooling & RH_COOL_COMPTON) {
+    const double zp1 = 1.0 / a;
+    Lam = Lam + (k.compton * zp1 * zp1 * zp1 * zp1) * (T - kTcmb0 * zp1) * ne;
+  }
+  q = (G - Lam) * (a3 / kMH) / nH;
+}
+
+// right-hand side of the adjoint Schur system: r = lE - (B^-1 C)^T lambda_loc
+__global__ void __launch_bounds__(kBlock)
+k_adj_rhs(StepK k, const double* __restrict__ lE, const double* __restrict__ le,
+          const double* __restrict__ ln, const double* __restrict__ BCn,
+          const double* __restrict__ BCe, double* __restrict__ r, double* __restrict__ part) {
+  double rmax = 0.0, r2 = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    double v = lE[idx] - BCn[idx] * ln[idx];
+    if (!k.iso) v -= BCe[idx] * le[idx];
+    r[idx] = v;
+    rmax = fmax(rmax, fabs(v));
+    r2 += v * v;
+  }
+  double vv[2] = {rmax, r2};
+  const int im[2] = {1, 0};
+  const int sl[2] = {RS_RMAX, RS_R2};
+  block_reduce_store<2>(vv, im, sl, part);
+}
+
+// Transposed local elimination and the local parts of (df/dU^n)^T mu,
+// (df/dn_H)^T mu and (df/dsrc)^T mu.  Slots: n, e, E, n_H, n^n, e^n, E^n.
+__global__ void __launch_bounds__(kBlock)
+k_adj_local(StepK k, AdjArgs a) {
+  const double a13 = k.a_1 * k.a_1 * k.a_1;
+  const double an3 = k.a_n * k.a_n * k.a_n;
+  const double th = k.theta, dt = k.dt;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    typedef DN<7> S;
+    const double nH = a.nH[idx];
+    S n = dn_var<7>(a.n1[idx], 0);
+    S e = dn_var<7>(k.iso ? 0.0 : a.e1[idx], 1);
+    S E = dn_var<7>(a.E1[idx], 2);
+    S H = dn_var<7>(nH, 3);
+    S nn = dn_var<7>(a.nn[idx], 4);
+    S en = dn_var<7>(k.iso ? 0.0 : a.en[idx], 5);
+    S En = dn_var<7>(a.En[idx], 6);
+    S A, B, q;
+    local_rates_nh<S>(k, E, e, n, H, k.a_1, A, B, q);
+    S numn = nn + (dt * th) * A;
+    S nume = en + (dt * th) * q;
+    if (k.theta_lt1) {
+      S An, Bn, qn;
+      local_rates_nh<S>(k, En, en, nn, H, k.a_n, An, Bn, qn);
+      numn = numn + (dt * (1.0 - th)) * (An - Bn * nn);
+      nume = nume + (dt * (1.0 - th)) * (qn - (2.0 * k.H_n) * en);
+    }
+    S fn = n - numn / (1.0 + (th * dt) * B);
+    const double muE = a.muE[idx];
+    const double JEn = dt * th * kC * k.sigma_E * a.E1[idx] / a13;
+    double mun, mue = 0.0;
+    S fe = dn_const<7>(0.0);
+    if (k.iso) {
+      mun = (a.ln[idx] - JEn * muE) / fn.g[0];
+    } else {
+      fe = e - nume / (1.0 + 2.0 * th * dt * k.H_1);
+      // B^T mu_loc = (ln - J_En mu_E, le),  B = [[fn_n, fn_e], [fe_n, fe_e]]
+      const double b11 = fn.g[0], b12 = fn.g[1], b21 = fe.g[0], b22 = fe.g[1];
+      const double r1 = a.ln[idx] - JEn * muE, r2 = a.le[idx];
+      const double idet = 1.0 / (b11 * b22 - b12 * b21);
+      mun = (b22 * r1 - b21 * r2) * idet;
+      mue = (-b12 * r1 + b11 * r2) * idet;
+    }
+    // local explicit parts of f_E (theta < 1)
+    double dfE_dEn = -1.0, dfE_dnn = 0.0;
+    if (k.theta_lt1) {
+      dfE_dEn += dt * (1.0 - th) * (k.H_n + kC * k.sigma_E * a.nn[idx] / an3);
+      dfE_dnn += dt * (1.0 - th) * kC * k.sigma_E * a.En[idx] / an3;
+    }
+    const double lnn = -(fn.g[4] * mun + fe.g[4] * mue) - dfE_dnn * muE;
+    const double lEn = -(fn.g[6] * mun + fe.g[6] * mue) - dfE_dEn * muE;
+    a.ln[idx] = lnn;
+    a.lE[idx] = lEn;
+    if (!k.iso) a.le[idx] = -(fn.g[5] * mun + fe.g[5] * mue);
+    a.g_nH[idx] += -(fn.g[3] * mun + fe.g[3] * mue);
+    a.g_src[idx] += dt * muE;
+  }
+}
+
+// Dependence of f_E on (E^n, n^n) through the lagged face limiter and the
+// explicit part: for every face f = (R, Q) of cell R,
+//   G_f = (mu_R - mu_Q) [ -c_f (E_Q - E_R) - c_f r_e (E^n_Q - E^n_R) ],
+// c_f = cf_scale D_f(E^n, kappa^n), r_e = (1-theta)/theta (a_1/a_n)^2;
+// lambda^n_R -= dG_f / d(E^n_R, n^n_R).  Outflow faces use the ghost
+// (E = E^n = E_floor, mu = 0, kappa = kappa_R).
+__global__ void __launch_bounds__(kBlock)
+k_adj_limiter(StepK k, AdjArgs a) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int nd[3] = {k.nx, k.ny, k.nz};
+  const double kfac = k.sigma_E / (k.a_n * k.a_n * k.a_n);
+  const double re = k.theta_lt1 ? k.expl_ratio : 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    typedef DN<2> S2;  // slots: E^n_R, kappa^n_R
+    const double EnR = a.En[idx], E1R = a.E1[idx], muR = a.muE[idx];
+    const S2 EnRd = dn_var<2>(EnR, 0);
+    const S2 kRd = dn_var<2>(kfac * a.nn[idx], 1);
+    double dE = 0.0, dk = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int q[3];
+        double EnQ, E1Q, muQ;
+        S2 kQd;
+        if (neighbour(c, nd, per, d, sgn, q)) {
+          const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
+          EnQ = a.En[Q];
+          E1Q = a.E1[Q];
+          muQ = a.muE[Q];
+          kQd = dn_const<2>(kfac * a.nn[Q]);
+        } else if (k.bc[2 * d + (sgn > 0 ? 1 : 0)] == RH_BC_OUTFLOW) {
+          EnQ = k.E_floor;
+          E1Q = k.E_floor;
+          muQ = 0.0;
+          kQd = kRd;
+        } else {
+          continue;  // zero-flux wall: no face term
+        }
+        // D on the face, differentiated w.r.t. this cell's E^n and kappa^n
+        const S2 Ebar = dfmax(0.5 * (EnRd + EnQ), k.E_floor);
+        const S2 R = dfmax(dfabs(EnQ - EnRd) / (Ebar * (k.a_n * k.h)), k.R_min);
+        const S2 kap = 0.5 * (kRd + kQd);
+        const S2 D = kC * (2.0 * kap + R) / (6.0 * kap * kap + 3.0 * kap * R + R * R);
+        const double cfv = k.cf_scale * D.v;
+        const double w = muR - muQ;
+        const double bracket = (E1Q - E1R) + re * (EnQ - EnR);
+        // G = -w c (bracket);  dG/dE^n_R = -w (dc/dE^n_R bracket - c re)
+        dE += w * (k.cf_scale * D.g[0] * bracket - cfv * re);
+        dk += w * (k.cf_scale * D.g[1] * bracket);
+      }
+    }
+    a.lE[idx] += dE;
+    a.ln[idx] += dk * kfac;
+  }
+}
+
+void launch_adj_rhs(hipStream_t s, const StepK& k, const double* lE, const double* le,
+                    const double* ln, const double* BCn, const double* BCe, double* r,
+                    double* part) {
+  hipLaunchKernelGGL(k_adj_rhs, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, lE, le, ln, BCn, BCe,
+                     r, part);
+}
+
+void launch_adj_local(hipStream_t s, const StepK& k, const AdjArgs& a) {
+  hipLaunchKernelGGL(k_adj_local, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a);
+}
+
+void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
+  hipLaunchKernelGGL(k_adj_limiter, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a);
+}
+
+// ---------------------------------------------------------------------------
 // explicit instantiations
 // ---------------------------------------------------------------------------
 #define RH_INST(T)                                                                            \

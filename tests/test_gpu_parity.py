@@ -174,3 +174,84 @@ def test_kernel_timing_does_not_change_results(hip_device):
     assert np.array_equal(E.cpu().numpy(), g0[0]) and np.array_equal(n.cpu().numpy(), g0[2])
     for k in ("local_solve", "residual_schur", "rbgs_fine", "pcg_direction"):
         assert kt[k][1] > 0 and kt[k][0] > 0, (k, kt[k])
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+ADJ_CASES = ["stromgren16", "lognormal_ragged", "eds_cooling16", "outflow_corner",
+             "theta06_smalldt"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", ADJ_CASES)
+def test_adjoint_step_parity(hip_device, case, precision):
+    """One adjoint step through the C ABI against the oracle's full sparse
+    transpose solve, on the same converged states and adjoint inputs."""
+    import paper_0908_2654_amd as P
+    from oracle import adjoint as OA, newton as ON
+    w = make_workload(case)
+    op, inp = oracle_inputs(w)
+    if w.sources == "random" and op.ncells > 8000:
+        pytest.skip("oracle transpose solve too large")
+    t0, dt = inp["t0"], inp["dt"]
+    Un = ON.step(op, t0, dt, inp["nH"], inp["src"], inp["E"], inp["e"], inp["n"], tol=1e-12)
+    U1 = ON.step(op, t0 + dt, dt, inp["nH"], inp["src"], *Un, tol=1e-12)
+    rng = np.random.default_rng(7)
+    lam = (rng.standard_normal(op.dims) / np.max(U1[0]), rng.standard_normal(op.dims) / np.max(U1[1]),
+           rng.standard_normal(op.dims) / inp["nH"])
+    lam_o = (lam[0], None if op.isothermal else lam[1], lam[2])
+    (oE, oe, on), ogs, ogh = OA.adjoint_step(op, t0 + dt, dt, inp["nH"], inp["src"], Un, U1, lam_o)
+    s = P.Solver(P.params_from_workload(w, precision=precision), device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    lE, le, ln = (d(x) for x in lam)
+    g_src = torch_zeros(op.dims, hip_device)
+    g_nH = torch_zeros(op.dims, hip_device)
+    st = s.adjoint_step(t0 + dt, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
+                        tuple(map(d, U1)), (lE, le, ln), g_src, g_nH)
+    s.close()
+    rel = lambda g, o: float(np.linalg.norm(g - o) / np.linalg.norm(o))  # noqa: E731
+    errs = {"lE": rel(lE.cpu().numpy(), oE), "ln": rel(ln.cpu().numpy(), on),
+            "g_src": rel(g_src.cpu().numpy(), ogs), "g_nH": rel(g_nH.cpu().numpy(), ogh)}
+    if not op.isothermal:
+        errs["le"] = rel(le.cpu().numpy(), oe)
+    print(case, precision, st["lin_its_total"], errs)
+    for k, v in errs.items():
+        assert v < 1e-9, (k, v)
+
+
+def torch_zeros(dims, dev):
+    import torch
+    return torch.zeros(dims, dtype=torch.float64, device=dev)
+
+
+@pytest.mark.parametrize("case,nsteps", [("stromgren16", 3), ("eds_cooling16", 2),
+                                         ("lognormal_ragged", 2)])
+def test_autograd_gradient_matches_oracle(hip_device, case, nsteps):
+    """dJ/dsrc and dJ/drho of J = mean x_HII through RHRun (forward steps,
+    checkpoints, adjoint steps) against the oracle's gradient."""
+    import torch
+
+    import paper_0908_2654_amd as P
+    from oracle import adjoint as OA
+    from paper_0908_2654_amd.autograd import RHRun
+    w = make_workload(case)
+    op, inp = oracle_inputs(w, newton_tol=1e-12)
+    J_o, gs_o, gh_o = OA.gradient(op, inp["t0"], inp["dt"], nsteps, inp["nH"], inp["src"],
+                                  w.x0, w.T0, w.E0, tol=1e-12)
+    s = P.Solver(P.params_from_workload(w, newton_tol=1e-12), device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    src = d(inp["src"]).requires_grad_(True)
+    nH = d(inp["nH"]).requires_grad_(True)
+    E0, e0 = d(inp["E"]), d(inp["e"])
+    n0 = (1.0 - w.x0) * nH
+    E, e, n = RHRun.apply(src, nH, E0, e0, n0, s, inp["t0"], inp["dt"], nsteps)
+    J = (1.0 - n / nH).mean()
+    gs, gh = torch.autograd.grad(J, (src, nH))
+    s.close()
+    rel = lambda g, o: float(np.linalg.norm(g - o) / np.linalg.norm(o))  # noqa: E731
+    print(case, "J", J.item(), J_o, "g_src", rel(gs.cpu().numpy(), gs_o), "g_nH",
+          rel(gh.cpu().numpy(), gh_o))
+    assert J.item() == pytest.approx(J_o, rel=1e-10)
+    assert rel(gs.cpu().numpy(), gs_o) < 1e-8
+    assert rel(gh.cpu().numpy(), gh_o) < 1e-8
