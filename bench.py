@@ -45,11 +45,31 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
     }.get(kind)
 
 
+def measured_traffic(kind, workload):
+    """HBM bytes per launch of `kind` from the committed counter record, or
+    None when there is none or the kernels have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload.split('_')[0]}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_0908_2654_amd", "csrc", "rh_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("class") != kind or rec.get("kernels_source_sha256") != sha:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(P, w, prec, inp, state, t_start, dt, steps, timing):
+def run_path(P, w, prec, inp, state, t_start, dt, steps, timing, adjoint=False):
+    """Time `steps` implicit steps; with adjoint=True also keep per-step
+    checkpoints (outside the timed region) and time the adjoint steps of
+    J = mean x_HII over the same steps, in reverse."""
     import torch
     prm = P.params_from_workload(w, precision=prec)
     s = P.Solver(prm, device=inp["nH"].device)
@@ -59,21 +79,54 @@ def run_path(P, w, prec, inp, state, t_start, dt, steps, timing):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
+    ckpt = [(E.clone(), e.clone(), n.clone())] if adjoint else None
+    t_ck = 0.0
     for k in range(steps):
         stats.append(s.step(t_start + k * dt, dt, inp["nH"], inp["src"], E, e, n))
+        if adjoint:
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            ckpt.append((E.clone(), e.clone(), n.clone()))
+            torch.cuda.synchronize()
+            t_ck += time.perf_counter() - tc
         log(f"  prec={prec} step {k}: newton={stats[-1]['newton_its']} "
             f"vcycles={stats[-1]['lin_its_total']} res={stats[-1]['res_final']:.2e} "
             f"gpu_ms={stats[-1]['t_ms'][0]:.1f}")
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall = time.perf_counter() - t0 - t_ck
     kt = s.kernel_timing() if timing else None
+    if timing:
+        s.set_kernel_timing(False)
+    adj = None
+    if adjoint:
+        N = w.ncells
+        lE = torch.zeros_like(E)
+        le = torch.zeros_like(E)
+        ln = -1.0 / (N * inp["nH"])
+        g_src = torch.zeros_like(E)
+        g_nH = torch.zeros_like(E)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ast = []
+        for k in reversed(range(steps)):
+            ast.append(s.adjoint_step(t_start + k * dt, dt, inp["nH"], inp["src"], ckpt[k],
+                                      ckpt[k + 1], (lE, le, ln), g_src, g_nH))
+        torch.cuda.synchronize()
+        wa = time.perf_counter() - ta
+        adj = {"ms_per_step": round(1e3 * wa / steps, 2),
+               "ratio_to_forward": round(wa / wall, 3),
+               "vcycles": [a["lin_its_total"] for a in ast],
+               "objective": "mean x_HII after the timed steps; gradients wrt src and n_H",
+               "finite": bool(torch.isfinite(g_src).all().item() and torch.isfinite(g_nH).all().item())}
+        log(f"  adjoint: {adj['ms_per_step']} ms/step, ratio {adj['ratio_to_forward']}")
+        del ckpt
     s.close()
     del s
     torch.cuda.empty_cache()
-    return wall, stats, kt, (E, e, n)
+    return wall, stats, kt, (E, e, n), adj
 
 
-def cpu_baseline(w, nH_full, t0, dt, sub=32):
+def cpu_baseline(w, nH_full, t0, dt, sub=64):
     """The oracle, as it stands, on a bounded sample: one implicit step of a
     sub^3 periodic sub-volume cut from the same workload (same cells, same
     density and sources inside it, same time and step)."""
@@ -113,10 +166,13 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the step has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -129,6 +185,15 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        # a plain copy of 2^28 float32 (1 GiB read, 1 GiB written), 3 times
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 << 28, "launches": 3}))
+        return
     w = W.get(args.config)
     log(f"workload {w.name} dims={w.dims}: generating inputs")
     tg = time.perf_counter()
@@ -149,14 +214,15 @@ def main():
     t_start = t0 + args.warmup * dt
     N = w.ncells
 
-    wall_m, st_m, kt_m, out_m = run_path(P, w, 1, inp, state, t_start, dt, args.steps, True)
+    wall_m, st_m, kt_m, out_m, adj = run_path(P, w, 1, inp, state, t_start, dt, args.steps, True,
+                                              adjoint=not args.no_adjoint)
     ms_m = 1e3 * wall_m / args.steps
     value = N * args.steps / wall_m / 1e6
     log(f"mixed: {ms_m:.1f} ms/step, {value:.1f} Mcell-updates/s")
 
     fp64 = None
     if not args.no_fp64:
-        wall_d, st_d, _, out_d = run_path(P, w, 0, inp, state, t_start, dt, args.steps, False)
+        wall_d, st_d, _, out_d, _ = run_path(P, w, 0, inp, state, t_start, dt, args.steps, False)
         fp64 = {"value": N * args.steps / wall_d / 1e6, "ms_per_step": 1e3 * wall_d / args.steps,
                 "newton_its": [s["newton_its"] for s in st_d],
                 "vcycles": [s["lin_its_total"] for s in st_d]}
@@ -177,10 +243,13 @@ def main():
     kind, ms, cnt, bpc = best
     avg_ms = ms / cnt
     achieved = bpc * N / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kind, w.name)
     roof = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_cell": bpc, "avg_launch_ms": round(avg_ms, 4),
-            "launches": cnt}
+            "traffic": None if traffic is None else round(traffic / 1e9, 3),
+            "traffic_unit": "GB per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_bytes_per_cell": None if traffic is None else round(traffic / N, 2),
+            "bytes_per_cell": bpc, "avg_launch_ms": round(avg_ms, 4), "launches": cnt}
     kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1]} for k, v in kt_m.items() if v[1]}
 
     cpu = None
@@ -209,6 +278,7 @@ def main():
                    "vcycles": [s["lin_its_total"] for s in st_m]},
         "fp64_path": fp64,
         "roofline": roof,
+        "adjoint": adj,
         "kernels_ms": kernels,
         "cpu_baseline": cpu,
     }
