@@ -29,10 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # and cache effects count zero).  T = 4 (mixed) or 8 (FP64) bytes.
 def algorithmic_bytes_per_cell(kind, T, iso=False):
     return {
-        # one colour of a red-black sweep: other-colour x, own b and diag,
-        # all three + face arrays (own + faces and the neighbours' - faces),
-        # own x written
-        "rbgs_fine": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
+        # one full red-black sweep in one launch: x, b, diag and the three
+        # + face arrays read, the new x written
+        "rbgs_fine": 7 * T,
+        # one colour of a sweep: other-colour x, own b and diag, all three
+        # + face arrays (own + faces and the neighbours' - faces), own x written
+        "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
         "mg_residual_fine": 6 * T + T,
         "restrict_fine": T + T / 8,
         "prolong_fine": T / 8 + 2 * T,
@@ -66,12 +68,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+MG = {}
+
+
 def run_path(P, w, prec, inp, state, t_start, dt, steps, timing, adjoint=False):
     """Time `steps` implicit steps; with adjoint=True also keep per-step
     checkpoints (outside the timed region) and time the adjoint steps of
     J = mean x_HII over the same steps, in reverse."""
     import torch
-    prm = P.params_from_workload(w, precision=prec)
+    prm = P.params_from_workload(w, precision=prec, **MG)
     s = P.Solver(prm, device=inp["nH"].device)
     E, e, n = (x.clone() for x in state)
     if timing:
@@ -167,6 +172,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--mg-pre", type=int, default=2)
+    ap.add_argument("--mg-post", type=int, default=2)
+    ap.add_argument("--smoother", type=int, default=0,
+                    help="0 auto, 1 one launch per colour, 2 fused sweep wherever it fits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -195,6 +204,7 @@ def main():
         print(json.dumps({"copy_bytes": 4 << 28, "launches": 3}))
         return
     w = W.get(args.config)
+    MG.update(mg_pre=args.mg_pre, mg_post=args.mg_post, smoother=args.smoother)
     log(f"workload {w.name} dims={w.dims}: generating inputs")
     tg = time.perf_counter()
     nH_host = W.density_field(w)
@@ -273,7 +283,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.dims), "sources": w.n_sources,
                    "steps_of_run": f"{args.warmup}..{args.warmup + args.steps - 1} of {nsteps}",
-                   "newton_tol": 1e-8, "lin_forcing": 1e-13, "outer": "PCG, V(2,2) preconditioner",
+                   "newton_tol": 1e-8, "lin_forcing": 1e-13, "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner",
                    "newton_its": [s["newton_its"] for s in st_m],
                    "vcycles": [s["lin_its_total"] for s in st_m]},
         "fp64_path": fp64,

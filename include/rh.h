@@ -95,6 +95,12 @@ typedef struct rh_params {
   int32_t krylov;              /* outer linear iteration: 1 = conjugate gradients with   */
                                /* the V-cycle as preconditioner (default), 0 = plain     */
                                /* defect correction x += V(b - S x)                      */
+  int32_t smoother;            /* red-black sweep form: 0 = auto (both colours in one    */
+                               /* marching launch on levels with >= 2048 of its tiles,   */
+                               /* else one launch per colour), 1 = always one launch per */
+                               /* colour, 2 = marching launch on every level its tiles   */
+                               /* fit (nz >= 64, ny >= 8, nx >= 4).  Same iterates up to */
+                               /* rounding order.                                        */
 } rh_params;
 
 /* Per-step statistics (host memory). */
@@ -188,11 +194,12 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
 /* Accumulated time (ms) and launch count per kernel class since the last
  * reset, for classes 0..n-1: 0 step setup (face limiter), 1 local solve,
  * 2 radiation residual + Schur diagonal, 3 reduction finalize, 4 red-black
- * Gauss-Seidel colour sweep on the finest level, 5 multigrid residual
+ * Gauss-Seidel sweep (both colours, one launch) on the finest level, 5 multigrid residual
  * (finest), 6 restriction (finest), 7 prolongation (finest), 8 coarse levels
  * (all work below the finest level), 9 conjugate-gradient direction and
  * S p, 10 conjugate-gradient update, 11 preconditioner rescale, 12 defect
- * correction update, 13 right-hand-side cast.  ms / counts are host arrays
+ * correction update, 13 right-hand-side cast, 14 one colour of a sweep on
+ * a finest level too small for the fused sweep.  ms / counts are host arrays
  * (either may be NULL); reset != 0 clears the totals afterwards. */
 rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
                                int32_t reset);

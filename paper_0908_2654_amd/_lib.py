@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(_PKG, "librh.so")
 
 KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rbgs_fine",
                   "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
-                  "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast"]
+                  "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast",
+                  "rbgs_fine_colour"]
 
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",
@@ -38,7 +39,7 @@ class RhParams(ctypes.Structure):
         ("newton_max_it", _i32), ("ls_max_cuts", _i32),
         ("lin_forcing", _f64),
         ("lin_max_it", _i32), ("mg_pre", _i32), ("mg_post", _i32), ("mg_coarse_max", _i32),
-        ("krylov", _i32),
+        ("krylov", _i32), ("smoother", _i32),
     ]
 
 

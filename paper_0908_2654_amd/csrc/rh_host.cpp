@@ -173,6 +173,7 @@ bool validate(const rh_params* p, std::string& err) {
   if (p->mg_pre < 1 || p->mg_post < 0 || p->mg_pre > 16 || p->mg_post > 16) { err = "mg_pre in [1,16], mg_post in [0,16]"; return false; }
   if (p->mg_coarse_max < 1 || p->mg_coarse_max > kCoarseMaxCells) { err = "mg_coarse_max in [1, 512]"; return false; }
   if (p->krylov != 0 && p->krylov != 1) { err = "krylov must be 0 or 1"; return false; }
+  if (p->smoother < 0 || p->smoother > 2) { err = "smoother must be 0, 1 or 2"; return false; }
   Plan pl;
   if (!plan_levels(*p, pl, err)) return false;
   return true;
@@ -207,7 +208,7 @@ struct StateBuf {
 
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
-  KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_COUNT
+  KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_COUNT
 };
 
 struct rh_handle {
@@ -288,6 +289,7 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
       L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
       for (int a = 0; a < 3; ++a) L.per[a] = per[a];
       L.x = cv.take<float>(n);
+      L.x2 = cv.take<float>(n);
       L.b = cv.take<float>(n);
       L.r = cv.take<float>(n);
       L.diag = cv.take<float>(n);
@@ -297,6 +299,7 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
       L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
       for (int a = 0; a < 3; ++a) L.per[a] = per[a];
       L.x = cv.take<double>(n);
+      L.x2 = cv.take<double>(n);
       L.b = cv.take<double>(n);
       L.r = cv.take<double>(n);
       if (l == 0) {
@@ -522,6 +525,26 @@ rh_status coarse_setup(rh_handle* h) {
   return RH_OK;
 }
 
+// One red-black sweep on level l: fused (x -> x2, then swap) when the level
+// fits the marching tiles, else colour by colour in place.
+template <class T>
+void sweep(rh_handle* h, int l, int first_color, int zero_init) {
+  LevelK<T>* L = levels<T>(h);
+  // auto: the fused sweep only where it gets enough workgroups to fill the chip
+  const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
+  if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
+    {
+      Timed tm(h, l == 0 ? KK_RBGS0 : KK_COARSE);
+      launch_rbgs_march<T>(h->stream, L[l], first_color, zero_init, l == 0, min_tiles);
+    }
+    std::swap(L[l].x, L[l].x2);
+    return;
+  }
+  const int kr = l == 0 ? KK_RBGS0C : KK_COARSE;
+  { Timed tm(h, kr); launch_rbgs<T>(h->stream, L[l], first_color, zero_init, l == 0); }
+  { Timed tm(h, kr); launch_rbgs<T>(h->stream, L[l], 1 - first_color, 0, l == 0); }
+}
+
 template <class T>
 void vcycle(rh_handle* h, int l) {
   LevelK<T>* L = levels<T>(h);
@@ -531,20 +554,13 @@ void vcycle(rh_handle* h, int l) {
     launch_coarsest_solve<T>(s, L[l], coarse_inverse<T>(h));
     return;
   }
-  const int kr = l == 0 ? KK_RBGS0 : KK_COARSE;
   // red first on the way down, black first on the way up: the cycle is symmetric
-  for (int it = 0; it < h->p.mg_pre; ++it) {
-    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 0, it == 0, l == 0); }
-    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 1, 0, l == 0); }
-  }
+  for (int it = 0; it < h->p.mg_pre; ++it) sweep<T>(h, l, 0, it == 0);
   { Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE); launch_mg_residual<T>(s, L[l]); }
   { Timed tm(h, l == 0 ? KK_RESTRICT0 : KK_COARSE); launch_restrict<T>(s, L[l], L[l + 1]); }
   vcycle<T>(h, l + 1);
   { Timed tm(h, l == 0 ? KK_PROLONG0 : KK_COARSE); launch_prolong<T>(s, L[l + 1], L[l]); }
-  for (int it = 0; it < h->p.mg_post; ++it) {
-    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 1, 0, l == 0); }
-    { Timed tm(h, kr); launch_rbgs<T>(s, L[l], 0, 0, l == 0); }
-  }
+  for (int it = 0; it < h->p.mg_post; ++it) sweep<T>(h, l, 1, 0);
 }
 
 // Defect correction: S dE = rS with V-cycles in T and FP64 residuals.
@@ -764,6 +780,7 @@ void rh_default_params(rh_params* p) {
   p->mg_post = 2;
   p->mg_coarse_max = 64;
   p->krylov = 1;
+  p->smoother = 0;
 }
 
 size_t rh_workspace_bytes(const rh_params* p) {

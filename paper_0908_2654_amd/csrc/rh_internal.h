@@ -49,6 +49,7 @@ struct LevelK {
   long long N;
   int per[3];           // periodic per dimension
   T* x;                 // correction
+  T* x2;                // second correction buffer (output of a fused sweep)
   T* b;                 // right-hand side
   T* r;                 // residual scratch
   T* diag;              // diagonal of the Schur operator
@@ -118,6 +119,16 @@ template <class T>
 void launch_coarsest_solve(hipStream_t s, const LevelK<T>& c, const T* InvT);
 template <class T>
 void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, int fine);
+// One full red-black sweep (first_color, then the other) reading l.x and
+// writing l.x2; returns false (nothing launched) unless rbgs_march_fits(l,
+// min_tiles), and the caller then sweeps colour by colour in place.
+template <class T>
+bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
+                       int fine, long long min_tiles);
+// The level has a second buffer, the shape the marching tiles need, fewer
+// than 2^31 cells and at least min_tiles tiles (one workgroup each).
+template <class T>
+bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles);
 template <class T>
 void launch_mg_residual(hipStream_t s, const LevelK<T>& l);
 template <class T>

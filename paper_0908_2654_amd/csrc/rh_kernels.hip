@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "rh_internal.h"
 
@@ -706,6 +707,192 @@ void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, in
     hipLaunchKernelGGL((k_rbgs<T, 0>), grid, dim3(kBlock), 0, s, l, color, zero_init);
 }
 
+// One full red-black sweep (both colours) in one launch, marching along x.
+// A block owns a TY x TZ tile of the (y, z) plane over XC consecutive x
+// planes.  x is read from l.x (never written during the sweep) into a ring
+// of four LDS planes with a 2-cell halo in y and z; the first colour is
+// updated on plane p over the tile plus a 1-cell ring (the ring values are
+// recomputed here, not written), then the second colour on plane p-1 over
+// the tile, and plane p-1 (both colours) is written to l.x2.  The first
+// colour is also recomputed on the plane before and after the block's x
+// range.  Every LDS slot stands for a real cell (periodic wrap) or for
+// "outside" (beyond a non-periodic wall); smoothed levels have all
+// dimensions even, so neighbours always have the other colour.  Reading one
+// buffer and writing another makes the result exactly that of a red sweep
+// followed by a black sweep, independent of block scheduling.
+//
+// Latency hiding: the next plane's x values are fetched into registers one
+// iteration ahead and stored to LDS after the current plane's updates; in
+// each colour phase a thread first issues the global loads of all its cells,
+// then computes.  Each thread works on fixed z-pairs (lz, lz+1) of the
+// region: exactly one cell of every pair has the colour being updated.
+template <class T, int TY, int TZ, int XC, int FINE>
+__global__ void __launch_bounds__(kBlock) k_rbgs_march(LevelK<T> l, int first_color, int zero_init) {
+  constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;
+  constexpr int NLOAD = (PL + kBlock - 1) / kBlock;                    // x slots per thread
+  constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + kBlock - 1) / kBlock;  // ring pairs per thread
+  constexpr int NBLK = (TY * TZ / 2 + kBlock - 1) / kBlock;             // tile pairs per thread
+  __shared__ T xs[4 * PL];
+  const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
+  int bid = blockIdx.x;
+  const int tz = bid % ntz;
+  bid /= ntz;
+  const int ty = bid % nty;
+  const int cx = bid / nty;
+  const int y0 = ty * TY - 2, z0 = tz * TZ - 2;  // global index of LDS slot 0 in y, z
+  const int xa = cx * XC, xb = min(xa + XC, l.nx);
+  const int plane = l.ny * l.nz;
+  auto wrap = [&](int g, int n, int per) -> int {
+    if (g >= 0 && g < n) return g;
+    if (!per) return -1;
+    return g < 0 ? g + n : g - n;
+  };
+  // in-plane offsets (or -1 outside) of this thread's x slots
+  int ld_off[NLOAD];
+#pragma unroll
+  for (int j = 0; j < NLOAD; ++j) {
+    const int t = threadIdx.x + j * kBlock;
+    ld_off[j] = -1;
+    if (t < PL) {
+      const int gy = wrap(y0 + t / HZ, l.ny, l.per[1]), gz = wrap(z0 + t % HZ, l.nz, l.per[2]);
+      if (gy >= 0 && gz >= 0) ld_off[j] = gy * l.nz + gz;
+    }
+  }
+  T pre[NLOAD];
+  auto fetch = [&](int p) {  // global -> registers
+    const int gx = wrap(p, l.nx, l.per[0]);
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j)
+      pre[j] = (!zero_init && gx >= 0 && ld_off[j] >= 0) ? l.x[gx * plane + ld_off[j]] : T(0);
+  };
+  auto stash = [&](int p) {  // registers -> LDS plane p
+    T* dst = xs + (((p % 4) + 4) % 4) * PL;
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) {
+      const int t = threadIdx.x + j * kBlock;
+      if (t < PL) dst[t] = pre[j];
+    }
+  };
+  // Update the cells of `color` on plane p over the region rows [lo, lo+ey),
+  // z-pairs [lo, lo+ez); NP = pairs per thread.  32-bit indices: the
+  // launcher only selects this kernel for levels below 2^31 cells.
+  auto update = [&](auto npc, int p, int color, int lo, int ey, int ez) {
+    constexpr int NP = decltype(npc)::value;
+    const int gx = wrap(p, l.nx, l.per[0]);
+    if (gx < 0) return;
+    T* cur = xs + (((p % 4) + 4) % 4) * PL;
+    const T* prv = xs + ((((p - 1) % 4) + 4) % 4) * PL;
+    const T* nxt = xs + ((((p + 1) % 4) + 4) % 4) * PL;
+    const int gxm = wrap(p - 1, l.nx, l.per[0]), gxp = wrap(p + 1, l.nx, l.per[0]);
+    const int pl = l.ny * l.nz;
+    const int half = ez / 2;
+    int s0[NP], msk[NP];
+    T bv[NP], dv[NP], c[NP][6];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int t = threadIdx.x + j * kBlock;
+      msk[j] = 0;
+      s0[j] = 0;
+      if (t >= ey * half) continue;
+      const int ly = lo + t / half;
+      const int gy = wrap(y0 + ly, l.ny, l.per[1]);
+      if (gy < 0) continue;
+      int lz = lo + 2 * (t % half);
+      int gz = wrap(z0 + lz, l.nz, l.per[2]);
+      if (((gx + gy + gz) & 1) != color) {
+        ++lz;
+        gz = wrap(z0 + lz, l.nz, l.per[2]);
+      }
+      if (gz < 0) continue;
+      s0[j] = ly * HZ + lz;
+      const int inpl = gy * l.nz + gz;
+      const int P = gx * pl + inpl;
+      const int gym = wrap(gy - 1, l.ny, l.per[1]), gzm = wrap(gz - 1, l.nz, l.per[2]);
+      const int m = 64 | (gxp >= 0) | ((gxm >= 0) << 1) | ((wrap(gy + 1, l.ny, l.per[1]) >= 0) << 2) |
+                    ((gym >= 0) << 3) | ((wrap(gz + 1, l.nz, l.per[2]) >= 0) << 4) |
+                    ((gzm >= 0) << 5);
+      msk[j] = m;
+      bv[j] = l.b[P];
+      dv[j] = l.diag[P];
+      c[j][0] = (m & 1) ? l.cf[0][P] : T(0);
+      c[j][1] = (m & 2) ? l.cf[0][gxm * pl + inpl] : T(0);
+      c[j][2] = (m & 4) ? l.cf[1][P] : T(0);
+      c[j][3] = (m & 8) ? l.cf[1][gx * pl + gym * l.nz + gz] : T(0);
+      c[j][4] = (m & 16) ? l.cf[2][P] : T(0);
+      c[j][5] = (m & 32) ? l.cf[2][gx * pl + gy * l.nz + gzm] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int m = msk[j];
+      if (!m) continue;
+      const int q = s0[j];
+      // same order as offdiag_sum: +x, -x, +y, -y, +z, -z
+      T off = 0;
+      if (m & 1) off += c[j][0] * nxt[q];
+      if (m & 2) off += c[j][1] * prv[q];
+      if (m & 4) off += c[j][2] * cur[q + HZ];
+      if (m & 8) off += c[j][3] * cur[q - HZ];
+      if (m & 16) off += c[j][4] * cur[q + 1];
+      if (m & 32) off += c[j][5] * cur[q - 1];
+      cur[q] = (bv[j] + off) / dv[j];
+    }
+  };
+  fetch(xa - 2);
+  stash(xa - 2);
+  fetch(xa - 1);
+  stash(xa - 1);
+  fetch(xa);
+  stash(xa);
+  __syncthreads();
+  for (int p = xa - 1; p <= xb; ++p) {
+    // planes p-1, p, p+1 are in LDS; fetch p+2 for the next iteration
+    if (p + 2 <= xb + 1) fetch(p + 2);
+    update(std::integral_constant<int, NRED>(), p, first_color, 1, TY + 2, TZ + 2);
+    __syncthreads();
+    const int q = p - 1;
+    if (q >= xa) {
+      update(std::integral_constant<int, NBLK>(), q, 1 - first_color, 2, TY, TZ);
+      __syncthreads();
+      const T* src = xs + (((q % 4) + 4) % 4) * PL;
+      for (int t = threadIdx.x; t < TY * TZ; t += kBlock) {
+        const int lz = t % TZ, ly = t / TZ;
+        const int gy = ty * TY + ly, gz = tz * TZ + lz;
+        if (gy < l.ny && gz < l.nz) l.x2[q * plane + gy * l.nz + gz] = src[(ly + 2) * HZ + lz + 2];
+      }
+    }
+    // plane p-2's buffer is free once plane q = p-1 is done
+    if (p + 2 <= xb + 1) stash(p + 2);
+    __syncthreads();
+  }
+}
+
+constexpr int kMarchTY = 8, kMarchTZ = 64, kMarchXC = 32;
+
+// The marching sweep needs enough tiles to fill the chip (it is not used on
+// small levels, where the colour-by-colour sweep has more parallelism).
+template <class T>
+bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles) {
+  if (!l.x2 || l.nz < kMarchTZ || l.ny < kMarchTY || l.nx < 4 || l.N >= (1LL << 31)) return false;
+  const long long nb = (long long)((l.ny + kMarchTY - 1) / kMarchTY) *
+                       ((l.nz + kMarchTZ - 1) / kMarchTZ) * ((l.nx + kMarchXC - 1) / kMarchXC);
+  return nb >= min_tiles;
+}
+
+template <class T>
+bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
+                       int fine, long long min_tiles) {
+  constexpr int TY = kMarchTY, TZ = kMarchTZ, XC = kMarchXC;
+  if (!rbgs_march_fits(l, min_tiles)) return false;
+  const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + XC - 1) / XC);
+  if (fine)
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, XC, 1>), dim3(nb), dim3(kBlock), 0, s, l,
+                       first_color, zero_init);
+  else
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, XC, 0>), dim3(nb), dim3(kBlock), 0, s, l,
+                       first_color, zero_init);
+  return true;
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_mg_residual(LevelK<T> l) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < l.N;
@@ -1242,6 +1429,8 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
                                            T*);                                               \
   template void launch_coarsest_solve<T>(hipStream_t, const LevelK<T>&, const T*);            \
   template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int, int);                 \
+  template bool launch_rbgs_march<T>(hipStream_t, const LevelK<T>&, int, int, int, long long); \
+  template bool rbgs_march_fits<T>(const LevelK<T>&, long long);                             \
   template void launch_mg_residual<T>(hipStream_t, const LevelK<T>&);                         \
   template void launch_restrict<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);          \
   template void launch_prolong<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);           \

@@ -14,7 +14,18 @@ CASES = {
     "outflow_corner": (0, (16, 16, 16), {
         "bc": (W.BC_ZEROFLUX, W.BC_OUTFLOW) * 3, "sources": "corner"}),
     "theta06_smalldt": (2, (16, 16, 16), {"theta": 0.6, "dt_Myr": 0.02}),
+    # tall grids: with smoother=2 the finest level runs the fused marching
+    # sweep (its tiles need nz >= 64, ny >= 8, nx >= 4)
+    "lognormal_tall": (2, (8, 16, 64), {"n_sources": 6}),
+    "stromgren_tall": (0, (8, 16, 64), {}),
 }
+
+# solver parameters per case (on top of the workload's)
+CASE_PARAMS = {"lognormal_tall": {"smoother": 2}, "stromgren_tall": {"smoother": 2}}
+
+
+def case_params(name):
+    return dict(CASE_PARAMS.get(name, {}))
 
 
 def make_workload(name):

@@ -5,7 +5,8 @@ and photoheated gas, theta = 1 and theta < 1, FP64 and mixed precision."""
 import numpy as np
 import pytest
 
-from gpu_cases import CASES, errors, gpu_trajectory, make_workload, oracle_inputs, to_dev
+from gpu_cases import (CASES, case_params, errors, gpu_trajectory, make_workload,
+                       oracle_inputs, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +66,8 @@ def test_residual_parity(hip_device, case):
 
 @pytest.mark.parametrize("krylov", [1, 0])
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner"])
+@pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner",
+                                  "lognormal_tall", "stromgren_tall"])
 def test_schur_solve_parity(hip_device, case, precision, krylov):
     import scipy.sparse.linalg as spla
 
@@ -87,8 +89,8 @@ def test_schur_solve_parity(hip_device, case, precision, krylov):
     S, _, _, _ = ON.schur_operator(op, loc, JEE, JEn, f[1], f[2], f[0])
     b = np.random.default_rng(3).standard_normal(op.ncells)
     x_ref = spla.spsolve(S.tocsc(), b)
-    s = P.Solver(P.params_from_workload(w, precision=precision, krylov=krylov),
-                 device=hip_device)
+    s = P.Solver(P.params_from_workload(w, precision=precision, krylov=krylov,
+                                        **case_params(case)), device=hip_device)
     d = lambda a: to_dev(a, hip_device)  # noqa: E731
     x, its, rr = s.schur_solve(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
                                tuple(map(d, U)), d(b.reshape(op.dims)), rel_tol=1e-13,
@@ -102,7 +104,8 @@ def test_schur_solve_parity(hip_device, case, precision, krylov):
 
 
 TRAJ = [("stromgren16", 20), ("lognormal_ragged", 2), ("eds_cooling16", 3),
-        ("outflow_corner", 3), ("theta06_smalldt", 2)]
+        ("outflow_corner", 3), ("theta06_smalldt", 2), ("lognormal_tall", 2),
+        ("stromgren_tall", 3)]
 
 
 @pytest.mark.parametrize("case,nsteps", TRAJ)
@@ -110,7 +113,8 @@ def test_step_parity_fp64(hip_device, case, nsteps):
     w = make_workload(case)
     op, inp = oracle_inputs(w, newton_tol=1e-12)
     o, ost = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
-    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=0)
+    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=0,
+                            **case_params(case))
     err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
     print(case, "fp64", err, [s["newton_its"] for s in gst], [s["lin_its_total"] for s in gst])
     assert err["E"] < 1e-10 and err["x"] < 1e-10
@@ -118,7 +122,8 @@ def test_step_parity_fp64(hip_device, case, nsteps):
         assert err["e"] < 1e-10
 
 
-MIXED = [("stromgren16", 5), ("lognormal_ragged", 2), ("eds_cooling16", 2)]
+MIXED = [("stromgren16", 5), ("lognormal_ragged", 2), ("eds_cooling16", 2),
+         ("lognormal_tall", 2)]
 
 
 @pytest.mark.parametrize("case,nsteps", MIXED)
@@ -128,7 +133,8 @@ def test_step_parity_mixed(hip_device, case, nsteps):
     w = make_workload(case)
     op, inp = oracle_inputs(w, newton_tol=1e-12)
     o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
-    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=1)
+    g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=1,
+                            **case_params(case))
     err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
     print(case, "mixed", err, [s["newton_its"] for s in gst], [s["lin_its_total"] for s in gst])
     assert err["E"] < 1e-6 and err["x"] < 1e-6
@@ -146,7 +152,8 @@ def test_step_mixed_at_timed_tolerance(hip_device, case, nsteps):
     o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
     res, out = {}, {}
     for prec in (0, 1):
-        g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-8, precision=prec)
+        g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-8, precision=prec,
+                                **case_params(case))
         out[prec] = g
         res[prec] = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-6)
         print(case, "timed prec", prec, res[prec], [s["newton_its"] for s in gst],
@@ -172,15 +179,46 @@ def test_kernel_timing_does_not_change_results(hip_device):
     kt = s.kernel_timing()
     s.close()
     assert np.array_equal(E.cpu().numpy(), g0[0]) and np.array_equal(n.cpu().numpy(), g0[2])
-    for k in ("local_solve", "residual_schur", "rbgs_fine", "pcg_direction"):
+    for k in ("local_solve", "residual_schur", "pcg_direction"):
         assert kt[k][1] > 0 and kt[k][0] > 0, (k, kt[k])
+    assert kt["rbgs_fine"][1] + kt["rbgs_fine_colour"][1] > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", ["lognormal_tall", "stromgren_tall"])
+def test_fused_sweep_matches_colour_sweeps(hip_device, case, precision):
+    """smoother=2 (both colours in one marching launch) and smoother=1 (one
+    launch per colour) run the same red-black iteration: the same Schur
+    solution to rounding, and the timing classes show which kernel ran."""
+    import paper_0908_2654_amd as P
+    w = make_workload(case)
+    op, inp = oracle_inputs(w)
+    Un, U = _perturbed_state(op, inp, seed=5)
+    t, dt = inp["t0"] + inp["dt"], inp["dt"]
+    b = np.random.default_rng(9).standard_normal(op.dims)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    xs, kts = {}, {}
+    for sm in (1, 2):
+        s = P.Solver(P.params_from_workload(w, precision=precision, smoother=sm),
+                     device=hip_device)
+        s.set_kernel_timing(True)
+        x, its, rr = s.schur_solve(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
+                                   tuple(map(d, U)), d(b), rel_tol=1e-13, max_it=300)
+        kts[sm] = s.kernel_timing()
+        s.close()
+        assert rr < 1e-12
+        xs[sm] = x.cpu().numpy()
+        print(case, precision, "smoother", sm, its, rr)
+    assert np.linalg.norm(xs[2] - xs[1]) / np.linalg.norm(xs[1]) < 1e-11
+    assert kts[1]["rbgs_fine"][1] == 0 and kts[1]["rbgs_fine_colour"][1] > 0
+    assert kts[2]["rbgs_fine"][1] > 0 and kts[2]["rbgs_fine_colour"][1] == 0
 
 
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
 ADJ_CASES = ["stromgren16", "lognormal_ragged", "eds_cooling16", "outflow_corner",
-             "theta06_smalldt"]
+             "theta06_smalldt", "stromgren_tall"]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -202,7 +240,8 @@ def test_adjoint_step_parity(hip_device, case, precision):
            rng.standard_normal(op.dims) / inp["nH"])
     lam_o = (lam[0], None if op.isothermal else lam[1], lam[2])
     (oE, oe, on), ogs, ogh = OA.adjoint_step(op, t0 + dt, dt, inp["nH"], inp["src"], Un, U1, lam_o)
-    s = P.Solver(P.params_from_workload(w, precision=precision), device=hip_device)
+    s = P.Solver(P.params_from_workload(w, precision=precision, **case_params(case)),
+                 device=hip_device)
     d = lambda a: to_dev(a, hip_device)  # noqa: E731
     lE, le, ln = (d(x) for x in lam)
     g_src = torch_zeros(op.dims, hip_device)
