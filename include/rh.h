@@ -99,8 +99,8 @@ typedef struct rh_params {
                                /* marching launch on levels with >= 2048 of its tiles,   */
                                /* else one launch per colour), 1 = always one launch per */
                                /* colour, 2 = marching launch on every level its tiles   */
-                               /* fit (nz >= 64, ny >= 8, nx >= 4).  Same iterates up to */
-                               /* rounding order.                                        */
+                               /* fit (nz >= 64 for FP32 levels, >= 32 for FP64; ny >= 8; */
+                               /* nx >= 4).  Same iterates up to rounding order.         */
 } rh_params;
 
 /* Per-step statistics (host memory). */
@@ -165,6 +165,20 @@ rh_status rh_residual(rh_handle* h, double t_n_s, double dt_s, const double* nH,
                       const double* nHI_n, const double* E, const double* e,
                       const double* nHI, double* fE, double* fe, double* fn,
                       double* norm_out);
+
+/* Write the Schur operator S of the Newton system at U = (E, e, nHI) of the
+ * step from U^n (Algorithm section: the radiation equation after the local
+ * unknowns are eliminated), the operator rh_schur_solve inverts:
+ *   (S x)_P = diag_P x_P - sum_d [cf_d,P x_{P+e_d} + cf_d,P-e_d x_{P-e_d}],
+ * where cf_d,P couples cell P with its + neighbour along axis d (x, y, z),
+ * wrapping on periodic axes; cf_d,P is 0 for the last cell along a
+ * non-periodic axis.  diag, cf_x, cf_y, cf_z: device fields (FP64, z
+ * fastest, caller-owned), overwritten; the call synchronises its stream. */
+rh_status rh_schur_operator(rh_handle* h, double t_n_s, double dt_s, const double* nH,
+                            const double* src, const double* E_n, const double* e_n,
+                            const double* nHI_n, const double* E, const double* e,
+                            const double* nHI, double* diag, double* cf_x, double* cf_y,
+                            double* cf_z);
 
 /* Solve S x = b with the configured multigrid (defect correction in FP64,
  * V-cycles in FP32 or FP64 by p->precision), where S is the Schur operator

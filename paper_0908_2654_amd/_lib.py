@@ -71,6 +71,8 @@ SIGNATURES = {
                            _vp, _vp, _vp, ctypes.POINTER(_f64)]),
     "rh_schur_solve": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp, _f64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]),
+    "rh_schur_operator": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, _vp]),
     "rh_get_constants": (_i32, [_vp, ctypes.POINTER(_f64), _i32]),
     "rh_cosmology_at": (_i32, [_PP, _f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "rh_cosmic_time": (_i32, [_PP, _f64, ctypes.POINTER(_f64)]),

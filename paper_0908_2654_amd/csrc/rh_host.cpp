@@ -956,6 +956,43 @@ rh_status rh_residual(rh_handle* h, double t_n, double dt, const double* nH, con
   return RH_OK;
 }
 
+// Face limiter from U^n, then the local elimination and the Schur operator
+// (diag64, cf64) at U; shared by rh_schur_solve and rh_schur_operator.
+static rh_status schur_at(rh_handle* h, StepK& k, const double* nH, const double* src,
+                          const double* E_n, const double* e_n, const double* nHI_n,
+                          const double* E, const double* e, const double* nHI) {
+  const bool iso = h->p.isothermal != 0;
+  rh_status st;
+  if ((st = copy_state(h, h->En, h->en, h->nn, E_n, e_n, nHI_n)) != RH_OK) return st;
+  if ((st = setup_step(h, k, src)) != RH_OK) return st;
+  StateBuf U{const_cast<double*>(E), iso ? nullptr : const_cast<double*>(e),
+             const_cast<double*>(nHI), {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
+  EvalOut ev{};
+  return eval_state(h, k, U, nullptr, 0.0, U, false, nH, 1, nullptr, nullptr, nullptr, ev);
+}
+
+rh_status rh_schur_operator(rh_handle* h, double t_n, double dt, const double* nH,
+                            const double* src, const double* E_n, const double* e_n,
+                            const double* nHI_n, const double* E, const double* e,
+                            const double* nHI, double* diag, double* cf_x, double* cf_y,
+                            double* cf_z) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, src, E_n, nHI_n, E, nHI, diag, cf_x, cf_y, cf_z});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e_n, e})) != RH_OK) return st;
+  if (!(dt > 0)) return fail(h, RH_EINVAL, "dt must be > 0");
+  StepK k = make_step(h, t_n, dt);
+  if ((st = schur_at(h, k, nH, src, E_n, e_n, nHI_n, E, e, nHI)) != RH_OK) return st;
+  const size_t bytes = sizeof(double) * h->N;
+  HIPCHK(hipMemcpyAsync(diag, h->diag64, bytes, hipMemcpyDeviceToDevice, h->stream));
+  double* out[3] = {cf_x, cf_y, cf_z};
+  for (int d = 0; d < 3; ++d)
+    HIPCHK(hipMemcpyAsync(out[d], h->cf64[d], bytes, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return RH_OK;
+}
+
 rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, const double* src,
                          const double* E_n, const double* e_n, const double* nHI_n,
                          const double* E, const double* e, const double* nHI, const double* b,
@@ -968,13 +1005,7 @@ rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, 
   if (!iso && (st = check_ptrs(h, {e_n, e})) != RH_OK) return st;
   if (!(dt > 0) || !(rel_tol >= 0) || max_it < 1) return fail(h, RH_EINVAL, "bad dt / tol / max_it");
   StepK k = make_step(h, t_n, dt);
-  if ((st = copy_state(h, h->En, h->en, h->nn, E_n, e_n, nHI_n)) != RH_OK) return st;
-  if ((st = setup_step(h, k, src)) != RH_OK) return st;
-  StateBuf U{const_cast<double*>(E), iso ? nullptr : const_cast<double*>(e),
-             const_cast<double*>(nHI), {h->locA[0], h->locA[1], h->locA[2], h->locA[3]}};
-  EvalOut ev{};
-  st = eval_state(h, k, U, nullptr, 0.0, U, false, nH, 1, nullptr, nullptr, nullptr, ev);
-  if (st != RH_OK) return st;
+  if ((st = schur_at(h, k, nH, src, E_n, e_n, nHI_n, E, e, nHI)) != RH_OK) return st;
   // right-hand side b replaces the Schur right-hand side; its norms first
   HIPCHK(hipMemcpyAsync(h->rS, b, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
   DefectArgs a{};

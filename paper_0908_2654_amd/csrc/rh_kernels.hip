@@ -721,167 +721,223 @@ void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, in
 // buffer and writing another makes the result exactly that of a red sweep
 // followed by a black sweep, independent of block scheduling.
 //
-// Latency hiding: the next plane's x values are fetched into registers one
-// iteration ahead and stored to LDS after the current plane's updates; in
-// each colour phase a thread first issues the global loads of all its cells,
-// then computes.  Each thread works on fixed z-pairs (lz, lz+1) of the
-// region: exactly one cell of every pair has the colour being updated.
+// Every global value is read once per block: besides x, the right-hand
+// side, the diagonal and the y/z face coefficients of a plane are staged in
+// LDS over rows [0, TY+3) and columns [0, TZ+3) of the halo coordinates
+// (two planes kept), and the x face coefficients over three planes, so a
+// cell's minus faces are its neighbours' staged plus faces.  Faces towards
+// "outside" are staged as 0 (the last cell along a non-periodic axis
+// already carries a 0 plus face), so the update needs no wall tests.  The
+// next plane's values are fetched into registers one iteration ahead and
+// stored to LDS after the current plane's updates.  Each thread updates
+// fixed z-pairs (lz, lz+1): exactly one cell of a pair has the colour.
+template <class T>
+struct MarchTile;
+template <>
+struct MarchTile<float> {
+  static constexpr int TY = 8, TZ = 64, XC = 32;
+};
+template <>
+struct MarchTile<double> {
+  static constexpr int TY = 8, TZ = 32, XC = 32;
+};
+
+__device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
+
 template <class T, int TY, int TZ, int XC, int FINE>
 __global__ void __launch_bounds__(kBlock) k_rbgs_march(LevelK<T> l, int first_color, int zero_init) {
-  constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;
-  constexpr int NLOAD = (PL + kBlock - 1) / kBlock;                    // x slots per thread
-  constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + kBlock - 1) / kBlock;  // ring pairs per thread
-  constexpr int NBLK = (TY * TZ / 2 + kBlock - 1) / kBlock;             // tile pairs per thread
+  static_assert(TZ % 2 == 0, "z-pairs need an even tile width");
+  constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
+  constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
+  constexpr int CP = CR * HZ;                               // coefficient plane (row stride HZ)
+  constexpr int NLX = (PL + kBlock - 1) / kBlock;
+  constexpr int NLC = (CN + kBlock - 1) / kBlock;
+  constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + kBlock - 1) / kBlock;
+  constexpr int NBLK = (TY * TZ / 2 + kBlock - 1) / kBlock;
   __shared__ T xs[4 * PL];
+  __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes p-1, p)
+  __shared__ T c0s[3 * CP];    // x faces (planes p-2, p-1, p)
   const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
   int bid = blockIdx.x;
   const int tz = bid % ntz;
   bid /= ntz;
   const int ty = bid % nty;
   const int cx = bid / nty;
-  const int y0 = ty * TY - 2, z0 = tz * TZ - 2;  // global index of LDS slot 0 in y, z
+  const int y0 = ty * TY - 2, z0 = tz * TZ - 2;  // global index of LDS row / column 0
   const int xa = cx * XC, xb = min(xa + XC, l.nx);
   const int plane = l.ny * l.nz;
+  const int tid = threadIdx.x;
   auto wrap = [&](int g, int n, int per) -> int {
     if (g >= 0 && g < n) return g;
     if (!per) return -1;
     return g < 0 ? g + n : g - n;
   };
-  // in-plane offsets (or -1 outside) of this thread's x slots
-  int ld_off[NLOAD];
+  auto inplane = [&](int ly, int lz) -> int {
+    const int gy = wrap(y0 + ly, l.ny, l.per[1]), gz = wrap(z0 + lz, l.nz, l.per[2]);
+    return (gy >= 0 && gz >= 0) ? gy * l.nz + gz : -1;
+  };
+  // in-plane offsets (or -1 outside) of this thread's staging slots
+  int xoff[NLX], coff[NLC];
 #pragma unroll
-  for (int j = 0; j < NLOAD; ++j) {
-    const int t = threadIdx.x + j * kBlock;
-    ld_off[j] = -1;
-    if (t < PL) {
-      const int gy = wrap(y0 + t / HZ, l.ny, l.per[1]), gz = wrap(z0 + t % HZ, l.nz, l.per[2]);
-      if (gy >= 0 && gz >= 0) ld_off[j] = gy * l.nz + gz;
-    }
+  for (int j = 0; j < NLX; ++j) {
+    const int t = tid + j * kBlock;
+    xoff[j] = t < PL ? inplane(t / HZ, t % HZ) : -1;
   }
-  T pre[NLOAD];
-  auto fetch = [&](int p) {  // global -> registers
+#pragma unroll
+  for (int j = 0; j < NLC; ++j) {
+    const int t = tid + j * kBlock;
+    coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
+  }
+  struct Buf {
+    T x[NLX];
+    T c[5][NLC];  // b, diag, y faces, z faces, x faces
+  };
+  auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, l.per[0]);
 #pragma unroll
-    for (int j = 0; j < NLOAD; ++j)
-      pre[j] = (!zero_init && gx >= 0 && ld_off[j] >= 0) ? l.x[gx * plane + ld_off[j]] : T(0);
+    for (int j = 0; j < NLX; ++j)
+      B.x[j] = (!zero_init && gx >= 0 && xoff[j] >= 0) ? l.x[gx * plane + xoff[j]] : T(0);
   };
-  auto stash = [&](int p) {  // registers -> LDS plane p
-    T* dst = xs + (((p % 4) + 4) % 4) * PL;
+  auto stash_x = [&](int p, const Buf& B) {
+    T* dst = xs + pmod(p, 4) * PL;
 #pragma unroll
-    for (int j = 0; j < NLOAD; ++j) {
-      const int t = threadIdx.x + j * kBlock;
-      if (t < PL) dst[t] = pre[j];
+    for (int j = 0; j < NLX; ++j) {
+      const int t = tid + j * kBlock;
+      if (t < PL) dst[t] = B.x[j];
     }
   };
-  // Update the cells of `color` on plane p over the region rows [lo, lo+ey),
-  // z-pairs [lo, lo+ez); NP = pairs per thread.  32-bit indices: the
-  // launcher only selects this kernel for levels below 2^31 cells.
+  auto fetch_c = [&](int p, bool all, Buf& B) {
+    const int gx = wrap(p, l.nx, l.per[0]);
+#pragma unroll
+    for (int j = 0; j < NLC; ++j) {
+      const bool ok = gx >= 0 && coff[j] >= 0;
+      const int P = ok ? gx * plane + coff[j] : 0;
+      B.c[4][j] = ok ? l.cf[0][P] : T(0);
+      if (all) {
+        B.c[0][j] = ok ? l.b[P] : T(0);
+        B.c[1][j] = ok ? l.diag[P] : T(1);
+        B.c[2][j] = ok ? l.cf[1][P] : T(0);
+        B.c[3][j] = ok ? l.cf[2][P] : T(0);
+      }
+    }
+  };
+  auto stash_c = [&](int p, bool all, const Buf& B) {
+    const int s2 = pmod(p, 2) * CP, s3 = pmod(p, 3) * CP;
+#pragma unroll
+    for (int j = 0; j < NLC; ++j) {
+      const int t = tid + j * kBlock;
+      if (t >= CN) continue;
+      const int li = (t / CZ) * HZ + t % CZ;
+      c0s[s3 + li] = B.c[4][j];
+      if (all) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cs[a][s2 + li] = B.c[a][j];
+      }
+    }
+  };
+  // Update the cells of `color` on plane p over rows [lo, lo+ey) and
+  // z-pairs starting at lo, lo+2, ... (ez columns); NP pairs per thread.
   auto update = [&](auto npc, int p, int color, int lo, int ey, int ez) {
     constexpr int NP = decltype(npc)::value;
-    const int gx = wrap(p, l.nx, l.per[0]);
-    if (gx < 0) return;
-    T* cur = xs + (((p % 4) + 4) % 4) * PL;
-    const T* prv = xs + ((((p - 1) % 4) + 4) % 4) * PL;
-    const T* nxt = xs + ((((p + 1) % 4) + 4) % 4) * PL;
-    const int gxm = wrap(p - 1, l.nx, l.per[0]), gxp = wrap(p + 1, l.nx, l.per[0]);
-    const int pl = l.ny * l.nz;
+    if (wrap(p, l.nx, l.per[0]) < 0) return;
+    T* cur = xs + pmod(p, 4) * PL;
+    const T* prv = xs + pmod(p - 1, 4) * PL;
+    const T* nxt = xs + pmod(p + 1, 4) * PL;
+    const int s2 = pmod(p, 2) * CP;
+    const T* cb = cs[0] + s2;
+    const T* cd = cs[1] + s2;
+    const T* c1 = cs[2] + s2;
+    const T* c2 = cs[3] + s2;
+    const T* c0c = c0s + pmod(p, 3) * CP;
+    const T* c0m = c0s + pmod(p - 1, 3) * CP;
     const int half = ez / 2;
-    int s0[NP], msk[NP];
-    T bv[NP], dv[NP], c[NP][6];
+    int qs[NP];
+    T nv[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      const int t = threadIdx.x + j * kBlock;
-      msk[j] = 0;
-      s0[j] = 0;
+      const int t = tid + j * kBlock;
+      qs[j] = -1;
       if (t >= ey * half) continue;
       const int ly = lo + t / half;
-      const int gy = wrap(y0 + ly, l.ny, l.per[1]);
-      if (gy < 0) continue;
       int lz = lo + 2 * (t % half);
-      int gz = wrap(z0 + lz, l.nz, l.per[2]);
-      if (((gx + gy + gz) & 1) != color) {
-        ++lz;
-        gz = wrap(z0 + lz, l.nz, l.per[2]);
-      }
-      if (gz < 0) continue;
-      s0[j] = ly * HZ + lz;
-      const int inpl = gy * l.nz + gz;
-      const int P = gx * pl + inpl;
-      const int gym = wrap(gy - 1, l.ny, l.per[1]), gzm = wrap(gz - 1, l.nz, l.per[2]);
-      const int m = 64 | (gxp >= 0) | ((gxm >= 0) << 1) | ((wrap(gy + 1, l.ny, l.per[1]) >= 0) << 2) |
-                    ((gym >= 0) << 3) | ((wrap(gz + 1, l.nz, l.per[2]) >= 0) << 4) |
-                    ((gzm >= 0) << 5);
-      msk[j] = m;
-      bv[j] = l.b[P];
-      dv[j] = l.diag[P];
-      c[j][0] = (m & 1) ? l.cf[0][P] : T(0);
-      c[j][1] = (m & 2) ? l.cf[0][gxm * pl + inpl] : T(0);
-      c[j][2] = (m & 4) ? l.cf[1][P] : T(0);
-      c[j][3] = (m & 8) ? l.cf[1][gx * pl + gym * l.nz + gz] : T(0);
-      c[j][4] = (m & 16) ? l.cf[2][P] : T(0);
-      c[j][5] = (m & 32) ? l.cf[2][gx * pl + gy * l.nz + gzm] : T(0);
+      if (((p + y0 + ly + z0 + lz) & 1) != color) ++lz;
+      if (wrap(y0 + ly, l.ny, l.per[1]) < 0 || wrap(z0 + lz, l.nz, l.per[2]) < 0) continue;
+      const int q = ly * HZ + lz;
+      qs[j] = q;
+      // same order as offdiag_sum: +x, -x, +y, -y, +z, -z
+      T off = c0c[q] * nxt[q];
+      off += c0m[q] * prv[q];
+      off += c1[q] * cur[q + HZ];
+      off += c1[q - HZ] * cur[q - HZ];
+      off += c2[q] * cur[q + 1];
+      off += c2[q - 1] * cur[q - 1];
+      nv[j] = (cb[q] + off) / cd[q];
     }
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      const int m = msk[j];
-      if (!m) continue;
-      const int q = s0[j];
-      // same order as offdiag_sum: +x, -x, +y, -y, +z, -z
-      T off = 0;
-      if (m & 1) off += c[j][0] * nxt[q];
-      if (m & 2) off += c[j][1] * prv[q];
-      if (m & 4) off += c[j][2] * cur[q + HZ];
-      if (m & 8) off += c[j][3] * cur[q - HZ];
-      if (m & 16) off += c[j][4] * cur[q + 1];
-      if (m & 32) off += c[j][5] * cur[q - 1];
-      cur[q] = (bv[j] + off) / dv[j];
-    }
+    for (int j = 0; j < NP; ++j)
+      if (qs[j] >= 0) cur[qs[j]] = nv[j];
   };
-  fetch(xa - 2);
-  stash(xa - 2);
-  fetch(xa - 1);
-  stash(xa - 1);
-  fetch(xa);
-  stash(xa);
+  Buf A, B;
+  fetch_x(xa - 2, A);
+  stash_x(xa - 2, A);
+  fetch_x(xa - 1, A);
+  stash_x(xa - 1, A);
+  fetch_x(xa, A);
+  stash_x(xa, A);
+  fetch_c(xa - 2, false, A);
+  stash_c(xa - 2, false, A);
+  fetch_c(xa - 1, true, A);
+  stash_c(xa - 1, true, A);
   __syncthreads();
-  for (int p = xa - 1; p <= xb; ++p) {
-    // planes p-1, p, p+1 are in LDS; fetch p+2 for the next iteration
-    if (p + 2 <= xb + 1) fetch(p + 2);
+  // registers run two planes ahead of LDS: plane p stores what plane p-1
+  // fetched (x of p+2, coefficients of p+1) and fetches x of p+3 and the
+  // coefficients of p+2 into the other buffer
+  fetch_x(xa + 1, A);
+  fetch_c(xa, true, A);
+  auto step = [&](int p, const Buf& now, Buf& ahead) {
+    // in LDS: x planes p-2..p+1, coefficients of p-1 and p, x faces of p-2..p
+    if (p + 3 <= xb + 1) fetch_x(p + 3, ahead);
+    if (p + 2 <= xb) fetch_c(p + 2, true, ahead);
     update(std::integral_constant<int, NRED>(), p, first_color, 1, TY + 2, TZ + 2);
     __syncthreads();
     const int q = p - 1;
     if (q >= xa) {
       update(std::integral_constant<int, NBLK>(), q, 1 - first_color, 2, TY, TZ);
       __syncthreads();
-      const T* src = xs + (((q % 4) + 4) % 4) * PL;
-      for (int t = threadIdx.x; t < TY * TZ; t += kBlock) {
+      const T* src = xs + pmod(q, 4) * PL;
+      for (int t = tid; t < TY * TZ; t += kBlock) {
         const int lz = t % TZ, ly = t / TZ;
         const int gy = ty * TY + ly, gz = tz * TZ + lz;
         if (gy < l.ny && gz < l.nz) l.x2[q * plane + gy * l.nz + gz] = src[(ly + 2) * HZ + lz + 2];
       }
     }
-    // plane p-2's buffer is free once plane q = p-1 is done
-    if (p + 2 <= xb + 1) stash(p + 2);
+    // the slots of plane p-2 (x) and p-1 (coefficients) are free once plane
+    // p-1 is done
+    if (p + 2 <= xb + 1) stash_x(p + 2, now);
+    if (p + 1 <= xb) stash_c(p + 1, true, now);
     __syncthreads();
+  };
+  for (int p = xa - 1; p <= xb; p += 2) {
+    step(p, A, B);
+    if (p + 1 <= xb) step(p + 1, B, A);
   }
 }
-
-constexpr int kMarchTY = 8, kMarchTZ = 64, kMarchXC = 32;
 
 // The marching sweep needs enough tiles to fill the chip (it is not used on
 // small levels, where the colour-by-colour sweep has more parallelism).
 template <class T>
 bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles) {
-  if (!l.x2 || l.nz < kMarchTZ || l.ny < kMarchTY || l.nx < 4 || l.N >= (1LL << 31)) return false;
-  const long long nb = (long long)((l.ny + kMarchTY - 1) / kMarchTY) *
-                       ((l.nz + kMarchTZ - 1) / kMarchTZ) * ((l.nx + kMarchXC - 1) / kMarchXC);
+  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ, XC = MarchTile<T>::XC;
+  if (!l.x2 || l.nz < TZ || l.ny < TY || l.nx < 4 || l.N >= (1LL << 31)) return false;
+  const long long nb = (long long)((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) *
+                       ((l.nx + XC - 1) / XC);
   return nb >= min_tiles;
 }
 
 template <class T>
 bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
                        int fine, long long min_tiles) {
-  constexpr int TY = kMarchTY, TZ = kMarchTZ, XC = kMarchXC;
+  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ, XC = MarchTile<T>::XC;
   if (!rbgs_march_fits(l, min_tiles)) return false;
   const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + XC - 1) / XC);
   if (fine)

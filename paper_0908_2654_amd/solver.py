@@ -152,6 +152,19 @@ class Solver:
         check(s, self._h)
         return fE, fe, fn, norm.value
 
+    def schur_operator(self, t, dt, nH, src, Un, U):
+        """The Schur operator at U: (diag, (cf_x, cf_y, cf_z)) with
+        (S x)_P = diag_P x_P - sum_d (cf_d,P x_{P+e_d} + cf_d,P-e_d x_{P-e_d})."""
+        En, en, nn = Un
+        E, e, n = U
+        diag = torch.empty_like(E)
+        cf = tuple(torch.empty_like(E) for _ in range(3))
+        s = lib.rh_schur_operator(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(En),
+                                  _ptr(en), _ptr(nn), _ptr(E), _ptr(e), _ptr(n), _ptr(diag),
+                                  *(_ptr(c) for c in cf))
+        check(s, self._h)
+        return diag, cf
+
     def schur_solve(self, t, dt, nH, src, Un, U, b, rel_tol=1e-12, max_it=100):
         """Solve S x = b with the Schur operator at U; returns (x, iters, rel_res)."""
         En, en, nn = Un

@@ -64,6 +64,72 @@ def test_residual_parity(hip_device, case):
     assert gnorm == pytest.approx(nrm, rel=1e-12)
 
 
+def _consistent_state(op, inp, seed):
+    """(U^n, U, t, dt) with U locally consistent (as Newton sees it)."""
+    from oracle import model as OM, newton as ON
+    Un, U = _perturbed_state(op, inp, seed=seed)
+    t, dt = inp["t0"] + inp["dt"], inp["dt"]
+    ctx = OM.make_context(op, t, dt, inp["nH"], inp["src"], *Un)
+    n_loc, e_loc = ON.local_solve(op, ctx, U[0], U[2], U[1])
+    e_loc = Un[1] if op.isothermal else e_loc
+    return Un, (U[0], e_loc, n_loc), t, dt, ctx
+
+
+@pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner",
+                                  "eds_cooling16", "theta06_smalldt"])
+def test_schur_operator_parity(hip_device, case):
+    """The exported Schur operator equals the oracle's assembled sparse S
+    entry by entry (diagonal and every off-diagonal coupling)."""
+    import scipy.sparse as sp
+
+    import paper_0908_2654_amd as P
+    from oracle import model as OM, newton as ON
+    w = make_workload(case)
+    op, inp = oracle_inputs(w)
+    Un, U, t, dt, ctx = _consistent_state(op, inp, seed=2)
+    ee = None if op.isothermal else U[1]
+    f = OM.residual(op, ctx, U[0], ee, U[2])
+    loc = ON.local_jacobian(op, ctx, U[0], ee, U[2])
+    JEE, JEn = ON.radiation_jacobian(op, ctx, U[0], U[2])
+    S = ON.schur_operator(op, loc, JEE, JEn, f[1], f[2], f[0])[0].tocsr()
+    s = P.Solver(P.params_from_workload(w), device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    diag, cf = s.schur_operator(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
+                                tuple(map(d, U)))
+    s.close()
+    diag = diag.cpu().numpy().ravel()
+    cf = [c.cpu().numpy() for c in cf]
+    # assemble the GPU operator as a sparse matrix from its documented form
+    N = op.ncells
+    idx = np.arange(N).reshape(op.dims)
+    rows, cols, vals = [np.arange(N)], [np.arange(N)], [diag]
+    for ax in range(3):
+        nb = np.roll(idx, -1, axis=ax)
+        keep = np.ones(op.dims, dtype=bool)
+        if op.bc[2 * ax] != 1:      # not periodic: the last cell has no + neighbour
+            sl = [slice(None)] * 3
+            sl[ax] = -1
+            keep[tuple(sl)] = False
+            assert np.all(cf[ax][tuple(sl)] == 0.0)
+        P_, Q_, c_ = idx[keep], nb[keep], cf[ax][keep]
+        rows += [P_, Q_]
+        cols += [Q_, P_]
+        vals += [-c_, -c_]
+    G = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N))
+    off_S = (S - sp.diags(S.diagonal())).tocsr()
+    off_G = (G - sp.diags(G.diagonal())).tocsr()
+    assert off_G.nnz == off_S.nnz            # same coupling pattern
+    floor = 1e-12 * abs(off_S).max()
+    Dm = abs(off_G - off_S).tocsr()
+    ref = abs(off_S).tocsr()
+    ref_at = np.asarray(ref[Dm.nonzero()]).ravel() if Dm.nnz else np.zeros(0)
+    off_err = float(np.max(Dm.data / np.maximum(ref_at, floor))) if Dm.nnz else 0.0
+    diag_err = np.max(np.abs(diag - S.diagonal()) / np.abs(S.diagonal()))
+    print(case, "off-diagonal rel", off_err, "diag rel", diag_err)
+    assert off_err < 1e-12 and diag_err < 1e-12
+
+
 @pytest.mark.parametrize("krylov", [1, 0])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner",
