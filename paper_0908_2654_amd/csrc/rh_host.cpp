@@ -276,7 +276,7 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
   h->B.n = cv.take<double>(N);
   for (int q = 0; q < 4; ++q) h->B.loc[q] = cv.take<double>(N);
   for (int q = 0; q < 4; ++q) h->locA[q] = cv.take<double>(N);
-  h->part = cv.take<double>((size_t)RS_COUNT * kRedBlocks);
+  h->part = cv.take<double>((size_t)RS_COUNT * kPartCap + RS_COUNT);
   h->redout = cv.take<double>(RS_COUNT);
   const bool mixed = p.precision == RH_PREC_MIXED;
   for (int l = 0; l < pl.nlev; ++l) {
@@ -400,7 +400,7 @@ struct Timed {
 rh_status sync_reductions(rh_handle* h, int nslots) {
   {
     Timed tm(h, KK_FINALIZE);
-    launch_finalize(h->stream, h->part, h->redout, nslots, h->N);
+    launch_finalize(h->stream, h->part, h->redout, nslots);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * nslots, hipMemcpyDeviceToHost,
@@ -828,7 +828,11 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
   hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&h->hred), sizeof(double) * RS_COUNT);
   hipError_t e3 = hipEventCreate(&h->ev0);
   hipError_t e4 = hipEventCreate(&h->ev1);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+  // no reducing kernel has run yet: every slot's block count is 0
+  hipError_t e5 = hipMemsetAsync(h->part + (size_t)RS_COUNT * kPartCap, 0,
+                                 sizeof(double) * RS_COUNT, h->stream);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
+      e5 != hipSuccess) {
     g_last_error = "HIP initialisation failed";
     delete h;
     return RH_EHIP;

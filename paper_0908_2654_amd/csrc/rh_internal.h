@@ -22,7 +22,12 @@ constexpr double kMpc = 3.0856775814913673e24;
 constexpr double kH100 = 1.0e7 / kMpc;     // 100 km/s/Mpc in 1/s
 
 constexpr int kBlock = 256;                // threads per block of the 1-D kernels
-constexpr int kRedBlocks = 1024;           // fixed grid of the reducing kernels
+constexpr int kRedBlocks = 2048;           // grid of the one-cell-per-thread reducing kernels
+// Block partial sums: part[slot * kPartCap + block]; each reducing kernel
+// also stores its block count at part[RS_COUNT * kPartCap + slot], which the
+// finalize pass reads, so kernels with different grids can share the buffer
+// (the last writer of a slot before a finalize defines it).
+constexpr int kPartCap = 16384;
 constexpr int kMaxLevels = 16;
 constexpr int kCoarseMaxCells = 512;
 
@@ -105,7 +110,7 @@ struct ResidArgs {
 void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* part);
 
 // Sums / maxima of the partials of a reducing launch over N fine cells.
-void launch_finalize(hipStream_t s, const double* part, double* out, int nslots, long long N);
+void launch_finalize(hipStream_t s, const double* part, double* out, int nslots);
 
 template <class Tin, class Tout>
 void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],

@@ -52,7 +52,8 @@ __device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max
     for (int q = 0; q < NV; ++q) {
       double v = sh[q][0];
       for (int w = 1; w < kBlock / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
-      part[(long long)slot[q] * kRedBlocks + blockIdx.x] = v;
+      part[(long long)slot[q] * kPartCap + blockIdx.x] = v;
+      if (blockIdx.x == 0) part[(long long)RS_COUNT * kPartCap + slot[q]] = (double)gridDim.x;
     }
   }
 }
@@ -484,16 +485,16 @@ void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* 
 // deterministic second pass of the reductions
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ part,
-                                                     double* __restrict__ out, int nslots,
-                                                     int nblocks) {
+                                                     double* __restrict__ out, int nslots) {
   __shared__ double sh[kBlock / 64];
   for (int s = 0; s < nslots; ++s) {
+    const int nblocks = (int)fmin(fmax(part[(long long)RS_COUNT * kPartCap + s], 0.0), (double)kPartCap);
     const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS ||
                          s == RS_EMAX || s == RS_SMAX || s == RS_NONFINITE ||
                          s == RS_BAD_RES);
     double v = is_max ? -INFINITY : 0.0;
     for (int b = threadIdx.x; b < nblocks; b += kBlock) {
-      double p = part[(long long)s * kRedBlocks + b];
+      double p = part[(long long)s * kPartCap + b];
       v = is_max ? fmax(v, p) : v + p;
     }
     v = is_max ? wave_max(v) : wave_sum(v);
@@ -508,8 +509,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   }
 }
 
-void launch_finalize(hipStream_t s, const double* part, double* out, int nslots, long long N) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, part, out, nslots, red_grid(N));
+void launch_finalize(hipStream_t s, const double* part, double* out, int nslots) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, part, out, nslots);
 }
 
 // ---------------------------------------------------------------------------
@@ -1148,9 +1149,203 @@ k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ c
   block_reduce_store<1>(v, im, sl, part);
 }
 
+// The same as k_pcg_dir, marching along x (the layout of k_rbgs_march): a
+// block owns a TY x TZ tile of the (y, z) plane over xc consecutive planes.
+// The current plane's p (tile + 1-cell ring) lives in LDS; each thread keeps
+// p of its own cells on the planes before and after in registers, and the
+// x face of the plane before; the y and z minus faces are read where the
+// block reads them as plus faces of its own cells (cache hits).  Loads are
+// issued one iteration before the one that consumes them.  The sum is formed
+// in the order of k_pcg_dir (+x, -x, +y, -y, +z, -z).
+constexpr int kDirTY = 8, kDirTZ = 64, kDirXC = 32;
+
+__global__ void __launch_bounds__(kBlock)
+k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restrict__ cfx,
+                const double* __restrict__ cfy, const double* __restrict__ cfz,
+                const double* __restrict__ z, const double* __restrict__ p_in,
+                double* __restrict__ p_out, double* __restrict__ q, double beta, int first, int xc,
+                double* __restrict__ part) {
+  constexpr int TY = kDirTY, TZ = kDirTZ, HZ = TZ + 2, PL = (TY + 2) * HZ;
+  constexpr int NR = TY / (kBlock / 64);  // own rows per thread
+  constexpr int NRING = 2 * TZ + 2 * TY;  // ring cells of a plane (no corners)
+  static_assert(TZ == 64 && NRING <= kBlock, "one wave per row, one ring cell per thread");
+  __shared__ double pl[2][PL];
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int ntz = (k.nz + TZ - 1) / TZ, nty = (k.ny + TY - 1) / TY;
+  int bid = blockIdx.x;
+  const int tz = bid % ntz;
+  bid /= ntz;
+  const int ty = bid % nty;
+  const int cx = bid / nty;
+  const int ya = ty * TY, za = tz * TZ;  // tile cell (0, 0) = LDS (1, 1)
+  const int xa = cx * xc, xb = min(xa + xc, k.nx);
+  const int plane = k.ny * k.nz;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  auto wrap = [&](int g, int n, int pr) -> int {
+    if (g >= 0 && g < n) return g;
+    if (!pr) return -1;
+    return g < 0 ? g + n : g - n;
+  };
+  auto off2 = [&](int gy, int gz) -> int {
+    const int wy = wrap(gy, k.ny, per[1]), wz = wrap(gz, k.nz, per[2]);
+    return (wy >= 0 && wz >= 0) ? wy * k.nz + wz : -1;
+  };
+  // own cells (rows wid + 4m, column lane); overhang cells of a ragged tile
+  // stand for their wrapped cell (or outside) and are not written
+  int own[NR], omy[NR], omz[NR], li[NR];
+  bool real[NR];
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    const int ly = wid + (kBlock / 64) * m, gy = ya + ly, gz = za + lane;
+    real[m] = gy < k.ny && gz < k.nz;
+    own[m] = off2(gy, gz);
+    omy[m] = off2(gy - 1, gz);
+    omz[m] = off2(gy, gz - 1);
+    li[m] = (ly + 1) * HZ + lane + 1;
+  }
+  // this thread's ring cell
+  int r_off = -1, r_li = -1;
+  if (threadIdx.x < NRING) {
+    const int e = threadIdx.x;
+    int ly, lz;
+    if (e < 2 * TZ) {
+      ly = e < TZ ? 0 : TY + 1;
+      lz = e % TZ + 1;
+    } else {
+      const int f = e - 2 * TZ;
+      ly = f % TY + 1;
+      lz = f < TY ? 0 : TZ + 1;
+    }
+    r_li = ly * HZ + lz;
+    r_off = off2(ya + ly - 1, za + lz - 1);
+  }
+  auto raw = [&](int p, int off, double& zv, double& pv) {
+    const int gx = wrap(p, k.nx, per[0]);
+    zv = 0.0;
+    pv = 0.0;
+    if (gx < 0 || off < 0) return;
+    const int P = gx * plane + off;
+    zv = z[P];
+    if (!first) pv = p_in[P];
+  };
+  auto form = [&](double zv, double pv) { return first ? zv : zv + beta * pv; };
+  struct Coef {
+    double d[NR], c0[NR], c1[NR], c2[NR], c1m[NR], c2m[NR];
+  };
+  auto load_coef = [&](int p, Coef& C) {
+    const int gx = wrap(p, k.nx, per[0]);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      const bool ok = gx >= 0 && own[m] >= 0;
+      const int P = ok ? gx * plane + own[m] : 0;
+      C.d[m] = ok ? diag[P] : 0.0;
+      C.c0[m] = ok ? cfx[P] : 0.0;
+      C.c1[m] = ok ? cfy[P] : 0.0;
+      C.c2[m] = ok ? cfz[P] : 0.0;
+      C.c1m[m] = (gx >= 0 && omy[m] >= 0) ? cfy[gx * plane + omy[m]] : 0.0;
+      C.c2m[m] = (gx >= 0 && omz[m] >= 0) ? cfz[gx * plane + omz[m]] : 0.0;
+    }
+  };
+  double pm[NR], pc[NR], pn[NR], c0m[NR];
+  double zo[NR], po[NR];  // own raw at x+2 (in flight)
+  double rz1, rp1, rz2, rp2;  // ring raw at x+1 (ready) and x+2 (in flight)
+  Coef C, Cn;
+  // prologue: planes xa-1, xa, xa+1 of p; plane xa in LDS; coefficients of xa
+  {
+    const int gxm = wrap(xa - 1, k.nx, per[0]);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      double a, b;
+      raw(xa - 1, own[m], a, b);
+      pm[m] = form(a, b);
+      raw(xa, own[m], a, b);
+      pc[m] = form(a, b);
+      raw(xa + 1, own[m], a, b);
+      pn[m] = form(a, b);
+      pl[xa & 1][li[m]] = pc[m];
+      c0m[m] = (gxm >= 0 && own[m] >= 0) ? cfx[gxm * plane + own[m]] : 0.0;
+    }
+    if (r_li >= 0) {
+      double a, b;
+      raw(xa, r_off, a, b);
+      pl[xa & 1][r_li] = form(a, b);
+      raw(xa + 1, r_off, rz1, rp1);
+    }
+    load_coef(xa, C);
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int x = xa; x < xb; ++x) {
+    // in flight for the next iteration
+    if (x + 1 < xb) load_coef(x + 1, Cn);
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      zo[m] = 0.0;
+      po[m] = 0.0;
+      if (x + 2 <= xb) raw(x + 2, own[m], zo[m], po[m]);
+    }
+    rz2 = rp2 = 0.0;
+    if (r_li >= 0 && x + 2 < xb) raw(x + 2, r_off, rz2, rp2);
+    // q on plane x
+    const double* L = pl[x & 1];
+    const int gx = x;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      if (!real[m]) continue;
+      const int t = li[m];
+      double off = C.c0[m] * pn[m];
+      off += c0m[m] * pm[m];
+      off += C.c1[m] * L[t + HZ];
+      off += C.c1m[m] * L[t - HZ];
+      off += C.c2[m] * L[t + 1];
+      off += C.c2m[m] * L[t - 1];
+      const double qv = C.d[m] * pc[m] - off;
+      const int P = gx * plane + own[m];
+      p_out[P] = pc[m];
+      q[P] = qv;
+      acc += pc[m] * qv;
+    }
+    // plane x+1 into the other LDS buffer (its readers finished before the
+    // last barrier)
+    if (x + 1 < xb) {
+      double* Ln = pl[(x + 1) & 1];
+#pragma unroll
+      for (int m = 0; m < NR; ++m) Ln[li[m]] = pn[m];
+      if (r_li >= 0) Ln[r_li] = form(rz1, rp1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      c0m[m] = C.c0[m];
+      pm[m] = pc[m];
+      pc[m] = pn[m];
+      pn[m] = form(zo[m], po[m]);
+    }
+    rz1 = rz2;
+    rp1 = rp2;
+    C = Cn;
+  }
+  double v[1] = {acc};
+  const int im[1] = {0};
+  const int sl[1] = {RS_PQ};
+  block_reduce_store<1>(v, im, sl, part);
+}
+
 void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
                     const double* z, const double* p_in, double* p_out, double* q, double beta,
                     int first, double* part) {
+  const int nty = (k.ny + kDirTY - 1) / kDirTY, ntz = (k.nz + kDirTZ - 1) / kDirTZ;
+  const long long tiles = (long long)nty * ntz;
+  if (k.nz >= kDirTZ && k.ny >= kDirTY && k.nx >= 2 && k.N < (1LL << 31) && tiles <= kPartCap) {
+    int ncx = (k.nx + kDirXC - 1) / kDirXC;
+    if (tiles * ncx > kPartCap) ncx = (int)(kPartCap / tiles);
+    const int xc = (k.nx + ncx - 1) / ncx;
+    ncx = (k.nx + xc - 1) / xc;
+    hipLaunchKernelGGL(k_pcg_dir_march, dim3((unsigned)(tiles * ncx)), dim3(kBlock), 0, s, k,
+                       diag, cf[0], cf[1], cf[2], z, p_in, p_out, q, beta, first, xc, part);
+    return;
+  }
   hipLaunchKernelGGL(k_pcg_dir, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, diag, cf[0], cf[1],
                      cf[2], z, p_in, p_out, q, beta, first, part);
 }
