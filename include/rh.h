@@ -95,12 +95,15 @@ typedef struct rh_params {
   int32_t krylov;              /* outer linear iteration: 1 = conjugate gradients with   */
                                /* the V-cycle as preconditioner (default), 0 = plain     */
                                /* defect correction x += V(b - S x)                      */
-  int32_t smoother;            /* red-black sweep form: 0 = auto (both colours in one    */
-                               /* marching launch on levels with >= 2048 of its tiles,   */
-                               /* else one launch per colour), 1 = always one launch per */
-                               /* colour, 2 = marching launch on every level its tiles   */
-                               /* fit (nz >= 64 for FP32 levels, >= 32 for FP64; ny >= 8; */
-                               /* nx >= 4).  Same iterates up to rounding order.         */
+  int32_t smoother;            /* multigrid kernel form: 0 = auto (the red-black sweep   */
+                               /* as one marching launch for both colours, and the       */
+                               /* residual fused with the restriction, on levels with    */
+                               /* >= 2048 of their tiles; elsewhere one launch per       */
+                               /* colour and separate residual and restriction), 1 =     */
+                               /* always the separate launches, 2 = the marching         */
+                               /* launches on every level their tiles fit (nz >= 64 for  */
+                               /* FP32 levels, >= 32 for FP64; ny >= 8; nx >= 4).  Same   */
+                               /* iterates up to rounding order.                         */
 } rh_params;
 
 /* Per-step statistics (host memory). */
@@ -209,7 +212,8 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
  * reset, for classes 0..n-1: 0 step setup (face limiter), 1 local solve,
  * 2 radiation residual + Schur diagonal, 3 reduction finalize, 4 red-black
  * Gauss-Seidel sweep (both colours, one launch) on the finest level, 5 multigrid residual
- * (finest), 6 restriction (finest), 7 prolongation (finest), 8 coarse levels
+ * (finest; fused with the restriction when the level takes the fused sweep), 6 restriction
+ * (finest, when not fused), 7 prolongation (finest), 8 coarse levels
  * (all work below the finest level), 9 conjugate-gradient direction and
  * S p, 10 conjugate-gradient update, 11 preconditioner rescale, 12 defect
  * correction update, 13 right-hand-side cast, 14 one colour of a sweep on

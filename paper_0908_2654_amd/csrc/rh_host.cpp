@@ -397,13 +397,13 @@ struct Timed {
   }
 };
 
-rh_status sync_reductions(rh_handle* h, int nslots) {
+rh_status sync_reductions(rh_handle* h, unsigned mask) {
   {
     Timed tm(h, KK_FINALIZE);
-    launch_finalize(h->stream, h->part, h->redout, nslots);
+    launch_finalize(h->stream, h->part, h->redout, mask);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * nslots, hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * RS_COUNT, hipMemcpyDeviceToHost,
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (h->timing) flush_timing(h);
@@ -424,7 +424,7 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
                       c32[0], c32[1], c32[2], h->rhsn, h->part);
   }
   HIPCHK(hipGetLastError());
-  rh_status st = sync_reductions(h, RS_COUNT);
+  rh_status st = sync_reductions(h, kAllSlots);
   if (st != RH_OK) return st;
   if (h->hred[RS_NONFINITE] != 0.0) return fail(h, RH_ENONFINITE, "non-finite E^n, n_HI^n or src");
   k.E_s = std::max(std::max(h->hred[RS_EMAX], k.dt * h->hred[RS_SMAX]), h->p.E_floor);
@@ -483,7 +483,7 @@ rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const do
     launch_residual(h->stream, k, r, h->part);
   }
   HIPCHK(hipGetLastError());
-  rh_status st = sync_reductions(h, RS_COUNT);
+  rh_status st = sync_reductions(h, kAllSlots);
   if (st != RH_OK) return st;
   const double* v = h->hred;
   const double s = v[RS_FE2] + v[RS_FN2] + (h->p.isothermal ? 0.0 : v[RS_FE_LOC2]);
@@ -545,6 +545,21 @@ void sweep(rh_handle* h, int l, int first_color, int zero_init) {
   { Timed tm(h, kr); launch_rbgs<T>(h->stream, L[l], 1 - first_color, 0, l == 0); }
 }
 
+// Residual of level l restricted into the right-hand side of level l+1: one
+// fused launch where the level takes the marching sweep, else two.
+template <class T>
+void residual_restrict(rh_handle* h, int l) {
+  LevelK<T>* L = levels<T>(h);
+  const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
+  if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
+    Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE);
+    launch_resid_restrict_march<T>(h->stream, L[l], L[l + 1], min_tiles);
+    return;
+  }
+  { Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE); launch_mg_residual<T>(h->stream, L[l]); }
+  { Timed tm(h, l == 0 ? KK_RESTRICT0 : KK_COARSE); launch_restrict<T>(h->stream, L[l], L[l + 1]); }
+}
+
 template <class T>
 void vcycle(rh_handle* h, int l) {
   LevelK<T>* L = levels<T>(h);
@@ -556,8 +571,7 @@ void vcycle(rh_handle* h, int l) {
   }
   // red first on the way down, black first on the way up: the cycle is symmetric
   for (int it = 0; it < h->p.mg_pre; ++it) sweep<T>(h, l, 0, it == 0);
-  { Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE); launch_mg_residual<T>(s, L[l]); }
-  { Timed tm(h, l == 0 ? KK_RESTRICT0 : KK_COARSE); launch_restrict<T>(s, L[l], L[l + 1]); }
+  residual_restrict<T>(h, l);
   vcycle<T>(h, l + 1);
   { Timed tm(h, l == 0 ? KK_PROLONG0 : KK_COARSE); launch_prolong<T>(s, L[l + 1], L[l]); }
   for (int it = 0; it < h->p.mg_post; ++it) sweep<T>(h, l, 1, 0);
@@ -606,7 +620,7 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
     }
     HIPCHK(hipGetLastError());
     sigma_b = rmax_cur;
-    st = sync_reductions(h, RS_COUNT);
+    st = sync_reductions(h, kAllSlots);
     if (st != RH_OK) return st;
     std::swap(dE_in, dE_out);
     first = false;
@@ -657,7 +671,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->z64, h->part);
   }
   HIPCHK(hipGetLastError());
-  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;
   double rz = h->hred[RS_ZR];
   double beta = 0.0, rmax_cur = rmax0;
   double w = INFINITY, l2 = INFINITY;
@@ -671,7 +685,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
                      h->part);
     }
     HIPCHK(hipGetLastError());
-    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    if ((st = sync_reductions(h, slot_bit(RS_PQ))) != RH_OK) return st;
     const double pq = h->hred[RS_PQ];
     if (!(pq > 0.0) || !std::isfinite(pq) || !(rz > 0.0)) {
       if (j == 1) return fail(h, RH_ELINEAR, "conjugate gradients broke down (S or V-cycle not positive)");
@@ -685,7 +699,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     }
     HIPCHK(hipGetLastError());
     sigma_b = rmax_cur;
-    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    if ((st = sync_reductions(h, slot_bit(RS_FE2) | slot_bit(RS_R2) | slot_bit(RS_RMAX))) != RH_OK) return st;
     *its_out = j;
     w = std::sqrt(h->hred[RS_FE2] / (h->N * nvars(h)));
     l2 = std::sqrt(h->hred[RS_R2]);
@@ -699,7 +713,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
       launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->z64, h->part);
     }
     HIPCHK(hipGetLastError());
-    if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+    if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;
     const double rz_new = h->hred[RS_ZR];
     beta = -alpha * h->hred[RS_ZQ] / rz;
     rz = rz_new;
@@ -1022,7 +1036,7 @@ rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, 
   else
     launch_accum_defect<double>(h->stream, k, a, nullptr, h->L64[0].r, h->part);
   HIPCHK(hipGetLastError());
-  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  if ((st = sync_reductions(h, kAllSlots)) != RH_OK) return st;
   const double bnorm = std::sqrt(h->hred[RS_R2]);
   const double bmax = h->hred[RS_RMAX];
   double* dE = nullptr;
@@ -1068,7 +1082,7 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   // S mu_E = lE - (B^-1 C)^T lambda_loc
   launch_adj_rhs(h->stream, k, lE, le, lnHI, h->locA[0], h->locA[1], h->rS, h->part);
   HIPCHK(hipGetLastError());
-  if ((st = sync_reductions(h, RS_COUNT)) != RH_OK) return st;
+  if ((st = sync_reductions(h, kAllSlots)) != RH_OK) return st;
   const double rnorm = std::sqrt(h->hred[RS_R2]);
   const double rmax = h->hred[RS_RMAX];
   if (!std::isfinite(rnorm)) return fail(h, RH_ENONFINITE, "non-finite adjoint right-hand side");

@@ -22,7 +22,7 @@ constexpr double kMpc = 3.0856775814913673e24;
 constexpr double kH100 = 1.0e7 / kMpc;     // 100 km/s/Mpc in 1/s
 
 constexpr int kBlock = 256;                // threads per block of the 1-D kernels
-constexpr int kRedBlocks = 2048;           // grid of the one-cell-per-thread reducing kernels
+constexpr int kRedBlocks = 1024;           // grid of the one-cell-per-thread reducing kernels
 // Block partial sums: part[slot * kPartCap + block]; each reducing kernel
 // also stores its block count at part[RS_COUNT * kPartCap + slot], which the
 // finalize pass reads, so kernels with different grids can share the buffer
@@ -79,6 +79,10 @@ enum RedSlot {
   RS_ZQ,           // sum z.q
   RS_COUNT
 };
+static_assert(RS_COUNT <= 32, "slot masks are 32-bit");
+constexpr unsigned kAllSlots = (1u << RS_COUNT) - 1;
+constexpr unsigned slot_bit(int s) { return 1u << s; }
+
 
 // ---- launchers (rh_kernels.hip) ------------------------------------------
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
@@ -110,7 +114,8 @@ struct ResidArgs {
 void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* part);
 
 // Sums / maxima of the partials of a reducing launch over N fine cells.
-void launch_finalize(hipStream_t s, const double* part, double* out, int nslots);
+// Reduces the slots whose bits are set in mask (bit s = slot s) into out[s].
+void launch_finalize(hipStream_t s, const double* part, double* out, unsigned mask);
 
 template <class Tin, class Tout>
 void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],
@@ -136,6 +141,12 @@ template <class T>
 bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles);
 template <class T>
 void launch_mg_residual(hipStream_t s, const LevelK<T>& l);
+// r = b - A x on f fused with the restriction of r into c.b (f.r is not
+// written); returns false (nothing launched) unless rbgs_march_fits(f,
+// min_tiles) and f has even dimensions.
+template <class T>
+bool launch_resid_restrict_march(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c,
+                                 long long min_tiles);
 template <class T>
 void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
 template <class T>

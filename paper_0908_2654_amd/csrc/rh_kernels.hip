@@ -484,33 +484,34 @@ void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* 
 // ---------------------------------------------------------------------------
 // deterministic second pass of the reductions
 // ---------------------------------------------------------------------------
+// One workgroup per reduction slot in `mask`: the slot's block partials in
+// a fixed order, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ part,
-                                                     double* __restrict__ out, int nslots) {
+                                                     double* __restrict__ out, unsigned mask) {
   __shared__ double sh[kBlock / 64];
-  for (int s = 0; s < nslots; ++s) {
-    const int nblocks = (int)fmin(fmax(part[(long long)RS_COUNT * kPartCap + s], 0.0), (double)kPartCap);
-    const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS ||
-                         s == RS_EMAX || s == RS_SMAX || s == RS_NONFINITE ||
-                         s == RS_BAD_RES);
-    double v = is_max ? -INFINITY : 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
-      double p = part[(long long)s * kPartCap + b];
-      v = is_max ? fmax(v, p) : v + p;
-    }
-    v = is_max ? wave_max(v) : wave_sum(v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = sh[0];
-      for (int w = 1; w < kBlock / 64; ++w) t = is_max ? fmax(t, sh[w]) : t + sh[w];
-      out[s] = t;
-    }
-    __syncthreads();
+  const int s = blockIdx.x;
+  if (!((mask >> s) & 1u)) return;
+  const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS || s == RS_EMAX ||
+                       s == RS_SMAX || s == RS_NONFINITE || s == RS_BAD_RES);
+  const int nblocks =
+      (int)fmin(fmax(part[(long long)RS_COUNT * kPartCap + s], 0.0), (double)kPartCap);
+  double v = is_max ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    const double p = part[(long long)s * kPartCap + b];
+    v = is_max ? fmax(v, p) : v + p;
+  }
+  v = is_max ? wave_max(v) : wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) t = is_max ? fmax(t, sh[w]) : t + sh[w];
+    out[s] = t;
   }
 }
 
-void launch_finalize(hipStream_t s, const double* part, double* out, int nslots) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, part, out, nslots);
+void launch_finalize(hipStream_t s, const double* part, double* out, unsigned mask) {
+  hipLaunchKernelGGL(k_finalize, dim3(RS_COUNT), dim3(kBlock), 0, s, part, out, mask);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,17 +737,18 @@ template <class T>
 struct MarchTile;
 template <>
 struct MarchTile<float> {
-  static constexpr int TY = 8, TZ = 64, XC = 32;
+  static constexpr int TY = 8, TZ = 64;
 };
 template <>
 struct MarchTile<double> {
-  static constexpr int TY = 8, TZ = 32, XC = 32;
+  static constexpr int TY = 8, TZ = 32;
 };
 
 __device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-template <class T, int TY, int TZ, int XC, int FINE>
-__global__ void __launch_bounds__(kBlock) k_rbgs_march(LevelK<T> l, int first_color, int zero_init) {
+template <class T, int TY, int TZ, int FINE>
+__global__ void __launch_bounds__(kBlock)
+k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
   static_assert(TZ % 2 == 0, "z-pairs need an even tile width");
   constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
   constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
@@ -765,7 +767,7 @@ __global__ void __launch_bounds__(kBlock) k_rbgs_march(LevelK<T> l, int first_co
   const int ty = bid % nty;
   const int cx = bid / nty;
   const int y0 = ty * TY - 2, z0 = tz * TZ - 2;  // global index of LDS row / column 0
-  const int xa = cx * XC, xb = min(xa + XC, l.nx);
+  const int xa = cx * xc, xb = min(xa + xc, l.nx);
   const int plane = l.ny * l.nz;
   const int tid = threadIdx.x;
   auto wrap = [&](int g, int n, int per) -> int {
@@ -924,29 +926,37 @@ __global__ void __launch_bounds__(kBlock) k_rbgs_march(LevelK<T> l, int first_co
   }
 }
 
-// The marching sweep needs enough tiles to fill the chip (it is not used on
-// small levels, where the colour-by-colour sweep has more parallelism).
+// x planes per block of the marching sweep: 32, or fewer (down to 8) when
+// that is what it takes to reach min_tiles workgroups; 0 when the level does
+// not fit the tiles (the caller then sweeps colour by colour).
+template <class T>
+int march_chunk(const LevelK<T>& l, long long min_tiles) {
+  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
+  if (!l.x2 || l.nz < TZ || l.ny < TY || l.nx < 4 || l.N >= (1LL << 31)) return 0;
+  const long long tiles = (long long)((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ);
+  for (int xc = 32; xc >= 8; xc /= 2)
+    if (tiles * ((l.nx + xc - 1) / xc) >= min_tiles) return xc;
+  return 0;
+}
+
 template <class T>
 bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles) {
-  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ, XC = MarchTile<T>::XC;
-  if (!l.x2 || l.nz < TZ || l.ny < TY || l.nx < 4 || l.N >= (1LL << 31)) return false;
-  const long long nb = (long long)((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) *
-                       ((l.nx + XC - 1) / XC);
-  return nb >= min_tiles;
+  return march_chunk(l, min_tiles) > 0;
 }
 
 template <class T>
 bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
                        int fine, long long min_tiles) {
-  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ, XC = MarchTile<T>::XC;
-  if (!rbgs_march_fits(l, min_tiles)) return false;
-  const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + XC - 1) / XC);
+  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
+  const int xc = march_chunk(l, min_tiles);
+  if (xc == 0) return false;
+  const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + xc - 1) / xc);
   if (fine)
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, XC, 1>), dim3(nb), dim3(kBlock), 0, s, l,
-                       first_color, zero_init);
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, 1>), dim3(nb), dim3(kBlock), 0, s, l,
+                       first_color, zero_init, xc);
   else
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, XC, 0>), dim3(nb), dim3(kBlock), 0, s, l,
-                       first_color, zero_init);
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, 0>), dim3(nb), dim3(kBlock), 0, s, l,
+                       first_color, zero_init, xc);
   return true;
 }
 
@@ -1003,6 +1013,234 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelK<T> f, LevelK<T> c) {
 template <class T>
 void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
   hipLaunchKernelGGL((k_restrict<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f, c);
+}
+
+// Residual r = b - A x on level f fused with the full-weighting restriction
+// of r into c.b (the arithmetic of k_mg_residual then k_restrict, in their
+// order), marching along fine x planes; r itself is not stored.  Tiles and
+// LDS staging are those of k_rbgs_march; a block owns TY x TZ fine cells of
+// the (y, z) plane and fine planes [xa, xb) (xa even), i.e. whole coarse
+// cells.  Per fine plane: r on the tile plus a 1-cell ring into an LDS plane
+// (two kept), then each owned coarse cell adds that plane's terms to its
+// running sum; a coarse plane is written once its fourth fine plane is in.
+// Restriction reads fold the stencil at non-periodic walls (the fine plane,
+// row or column 0 stands for -1, and n-1 for n); one barrier per plane.
+template <class T, int TY, int TZ>
+__global__ void __launch_bounds__(kBlock)
+k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
+  static_assert(TZ % 2 == 0 && TY % 2 == 0, "tiles hold whole coarse cells");
+  constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
+  constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
+  constexpr int CP = CR * HZ;
+  constexpr int NLX = (PL + kBlock - 1) / kBlock;
+  constexpr int NLC = (CN + kBlock - 1) / kBlock;
+  constexpr int RR = TY + 2, RZ = TZ + 2, RN = RR * RZ;   // residual slots: rows/cols 1..
+  constexpr int NRES = (RN + kBlock - 1) / kBlock;
+  constexpr int NCC = (TY / 2) * (TZ / 2);                 // coarse cells per tile
+  static_assert(NCC <= kBlock, "one coarse cell per thread");
+  __shared__ T xs[4 * PL];
+  __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes i, i+1)
+  __shared__ T c0s[3 * CP];    // x faces (planes i-1, i, i+1)
+  __shared__ T rs[2][CP];      // residual planes (same coordinates)
+  const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
+  int bid = blockIdx.x;
+  const int tz = bid % ntz;
+  bid /= ntz;
+  const int ty = bid % nty;
+  const int cx = bid / nty;
+  const int y0 = ty * TY - 2, z0 = tz * TZ - 2;  // global index of LDS row / column 0
+  const int xa = cx * xc, xb = min(xa + xc, l.nx);
+  const int plane = l.ny * l.nz;
+  const int tid = threadIdx.x;
+  const int px = l.per[0];
+  auto wrap = [&](int g, int n, int per) -> int {
+    if (g >= 0 && g < n) return g;
+    if (!per) return -1;
+    return g < 0 ? g + n : g - n;
+  };
+  auto inplane = [&](int ly, int lz) -> int {
+    const int gy = wrap(y0 + ly, l.ny, l.per[1]), gz = wrap(z0 + lz, l.nz, l.per[2]);
+    return (gy >= 0 && gz >= 0) ? gy * l.nz + gz : -1;
+  };
+  int xoff[NLX], coff[NLC];
+#pragma unroll
+  for (int j = 0; j < NLX; ++j) {
+    const int t = tid + j * kBlock;
+    xoff[j] = t < PL ? inplane(t / HZ, t % HZ) : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < NLC; ++j) {
+    const int t = tid + j * kBlock;
+    coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
+  }
+  // residual slots of this thread (LDS index, or -1 when outside the grid)
+  int rq[NRES];
+#pragma unroll
+  for (int j = 0; j < NRES; ++j) {
+    const int t = tid + j * kBlock;
+    rq[j] = -1;
+    if (t < RN) {
+      const int ly = 1 + t / RZ, lz = 1 + t % RZ;
+      if (inplane(ly, lz) >= 0) rq[j] = ly * HZ + lz;
+    }
+  }
+  // this thread's coarse cell and the LDS rows / columns of its stencil
+  const bool has_cc = tid < NCC;
+  const int cj = tid / (TZ / 2), ck = tid % (TZ / 2);
+  const int J = ty * (TY / 2) + cj, K = tz * (TZ / 2) + ck;
+  const bool cc_real = has_cc && J < c.ny && K < c.nz;
+  int srow[4], scol[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int vy = 2 * J - 1 + b, vz = 2 * K - 1 + b;
+    srow[b] = (l.per[1] ? vy : fold(vy, l.ny, 0)) - y0;
+    scol[b] = (l.per[2] ? vz : fold(vz, l.nz, 0)) - z0;
+  }
+  struct Buf {
+    T x[NLX];
+    T c[5][NLC];
+  };
+  auto fetch_x = [&](int p, Buf& B) {
+    const int gx = wrap(p, l.nx, px);
+#pragma unroll
+    for (int j = 0; j < NLX; ++j)
+      B.x[j] = (gx >= 0 && xoff[j] >= 0) ? l.x[gx * plane + xoff[j]] : T(0);
+  };
+  auto stash_x = [&](int p, const Buf& B) {
+    T* dst = xs + pmod(p, 4) * PL;
+#pragma unroll
+    for (int j = 0; j < NLX; ++j) {
+      const int t = tid + j * kBlock;
+      if (t < PL) dst[t] = B.x[j];
+    }
+  };
+  auto fetch_c = [&](int p, bool all, Buf& B) {
+    const int gx = wrap(p, l.nx, px);
+#pragma unroll
+    for (int j = 0; j < NLC; ++j) {
+      const bool ok = gx >= 0 && coff[j] >= 0;
+      const int P = ok ? gx * plane + coff[j] : 0;
+      B.c[4][j] = ok ? l.cf[0][P] : T(0);
+      if (all) {
+        B.c[0][j] = ok ? l.b[P] : T(0);
+        B.c[1][j] = ok ? l.diag[P] : T(0);
+        B.c[2][j] = ok ? l.cf[1][P] : T(0);
+        B.c[3][j] = ok ? l.cf[2][P] : T(0);
+      }
+    }
+  };
+  auto stash_c = [&](int p, bool all, const Buf& B) {
+    const int s2 = pmod(p, 2) * CP, s3 = pmod(p, 3) * CP;
+#pragma unroll
+    for (int j = 0; j < NLC; ++j) {
+      const int t = tid + j * kBlock;
+      if (t >= CN) continue;
+      const int li = (t / CZ) * HZ + t % CZ;
+      c0s[s3 + li] = B.c[4][j];
+      if (all) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) cs[a][s2 + li] = B.c[a][j];
+      }
+    }
+  };
+  // fine planes whose residual this block needs: xa-1 .. xb (periodic), or
+  // clipped to the grid (the fold repeats planes 0 and nx-1)
+  const int i0 = px ? xa - 1 : max(xa - 1, 0);
+  const int i1 = px ? xb : min(xb, l.nx - 1);
+  const double w[4] = {0.125, 0.375, 0.375, 0.125};
+  const int cplane = c.ny * c.nz;
+  const int Ilo = xa / 2, Ihi = xb / 2;  // coarse planes [Ilo, Ihi) of this block
+  double acc[2] = {0.0, 0.0};
+  // add fine plane i's terms as stencil position a of coarse plane I
+  auto add_terms = [&](const double (&sz)[4], int I, int a) {
+    if (I < Ilo || I >= Ihi) return;
+    double& s = acc[I & 1];
+    if (a == 0) s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s += w[a] * w[b] * sz[b];
+    if (a == 3 && cc_real) c.b[I * cplane + J * c.nz + K] = (T)s;
+  };
+  Buf A, B;
+  fetch_x(i0 - 1, A);
+  stash_x(i0 - 1, A);
+  fetch_x(i0, A);
+  stash_x(i0, A);
+  fetch_x(i0 + 1, A);
+  stash_x(i0 + 1, A);
+  fetch_c(i0 - 1, false, A);
+  stash_c(i0 - 1, false, A);
+  fetch_c(i0, true, A);
+  stash_c(i0, true, A);
+  fetch_x(i0 + 2, A);
+  fetch_c(i0 + 1, true, A);
+  __syncthreads();
+  auto step = [&](int i, const Buf& now, Buf& ahead) {
+    // in LDS: x planes i-1..i+1, coefficients of i, x faces of i-1 and i
+    if (i + 3 <= i1 + 1) fetch_x(i + 3, ahead);
+    if (i + 2 <= i1) fetch_c(i + 2, true, ahead);
+    {
+      const T* cur = xs + pmod(i, 4) * PL;
+      const T* prv = xs + pmod(i - 1, 4) * PL;
+      const T* nxt = xs + pmod(i + 1, 4) * PL;
+      const int s2 = pmod(i, 2) * CP;
+      const T* cb = cs[0] + s2;
+      const T* cd = cs[1] + s2;
+      const T* c1 = cs[2] + s2;
+      const T* c2 = cs[3] + s2;
+      const T* c0c = c0s + pmod(i, 3) * CP;
+      const T* c0m = c0s + pmod(i - 1, 3) * CP;
+      T* r = rs[i & 1];
+#pragma unroll
+      for (int j = 0; j < NRES; ++j) {
+        const int q = rq[j];
+        if (q < 0) continue;
+        // k_mg_residual: b - (diag x - offdiag), offdiag in the order of offdiag_sum
+        T off = 0;
+        off += c0c[q] * nxt[q];
+        off += c0m[q] * prv[q];
+        off += c1[q] * cur[q + HZ];
+        off += c1[q - HZ] * cur[q - HZ];
+        off += c2[q] * cur[q + 1];
+        off += c2[q - 1] * cur[q - 1];
+        r[q] = cb[q] - (cd[q] * cur[q] - off);
+      }
+    }
+    if (i + 2 <= i1 + 1) stash_x(i + 2, now);
+    if (i + 1 <= i1) stash_c(i + 1, true, now);
+    __syncthreads();
+    if (cc_real) {
+      const T* r = rs[i & 1];
+      double sz[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double t = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) t += w[d] * (double)r[srow[b] * HZ + scol[d]];
+        sz[b] = t;
+      }
+      // fine plane i is stencil position a = i + 1 - 2I of coarse plane I
+      const int Ia = (i + 1) >> 1;  // positions 0 / 1
+      if (!px && i == 0) add_terms(sz, 0, 0);              // plane -1 folds onto 0
+      add_terms(sz, Ia, i + 1 - 2 * Ia);
+      add_terms(sz, Ia - 1, i + 3 - 2 * Ia);               // positions 2 / 3
+      if (!px && i == l.nx - 1) add_terms(sz, c.nx - 1, 3);  // plane nx folds onto nx-1
+    }
+  };
+  for (int i = i0; i <= i1; i += 2) {
+    step(i, A, B);
+    if (i + 1 <= i1) step(i + 1, B, A);
+  }
+}
+
+template <class T>
+bool launch_resid_restrict_march(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c,
+                                 long long min_tiles) {
+  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
+  const int xc = march_chunk(f, min_tiles);
+  if (xc == 0 || f.nx % 2 || f.ny % 2 || f.nz % 2) return false;
+  const int nb = ((f.ny + TY - 1) / TY) * ((f.nz + TZ - 1) / TZ) * ((f.nx + xc - 1) / xc);
+  hipLaunchKernelGGL((k_resid_restrict_march<T, TY, TZ>), dim3(nb), dim3(kBlock), 0, s, f, c, xc);
+  return true;
 }
 
 // Trilinear cell-centred prolongation (weights 3/4, 1/4 per axis), added to x.
@@ -1682,6 +1920,8 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
   template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int, int);                 \
   template bool launch_rbgs_march<T>(hipStream_t, const LevelK<T>&, int, int, int, long long); \
   template bool rbgs_march_fits<T>(const LevelK<T>&, long long);                             \
+  template bool launch_resid_restrict_march<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&, \
+                                               long long);                                    \
   template void launch_mg_residual<T>(hipStream_t, const LevelK<T>&);                         \
   template void launch_restrict<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);          \
   template void launch_prolong<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);           \
