@@ -101,9 +101,9 @@ typedef struct rh_params {
                                /* >= 2048 of their tiles; elsewhere one launch per       */
                                /* colour and separate residual and restriction), 1 =     */
                                /* always the separate launches, 2 = the marching         */
-                               /* launches on every level their tiles fit (nz >= 64 for  */
-                               /* FP32 levels, >= 32 for FP64; ny >= 8; nx >= 4).  Same   */
-                               /* iterates up to rounding order.                         */
+                               /* launches on every level their tiles fit (FP32 levels:  */
+                               /* nz >= 64, ny >= 16; FP64: nz >= 32, ny >= 8; nx >= 4). */
+                               /* Same iterates up to rounding order.                    */
 } rh_params;
 
 /* Per-step statistics (host memory). */

@@ -223,7 +223,7 @@ struct rh_handle {
   size_t ws_bytes;
   // fine FP64 fields
   double *En, *en, *nn, *rhsn, *rS, *diag64, *dEa, *dEb;
-  double *r64, *pa, *pb, *q64, *z64;  // conjugate-gradient vectors
+  double *r64, *pa, *pb, *q64;  // conjugate-gradient vectors
   double* cf64[3];
   StateBuf B;
   double* locA[4];
@@ -268,7 +268,6 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
     h->pa = cv.take<double>(N);
     h->pb = cv.take<double>(N);
     h->q64 = cv.take<double>(N);
-    h->z64 = cv.take<double>(N);
   }
   for (int d = 0; d < 3; ++d) h->cf64[d] = cv.take<double>(N);
   h->B.E = cv.take<double>(N);
@@ -551,7 +550,7 @@ template <class T>
 void residual_restrict(rh_handle* h, int l) {
   LevelK<T>* L = levels<T>(h);
   const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
-  if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
+  if (h->p.smoother != 1 && resid_restrict_fits<T>(L[l], min_tiles)) {
     Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE);
     launch_resid_restrict_march<T>(h->stream, L[l], L[l + 1], min_tiles);
     return;
@@ -668,7 +667,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
   vcycle<T>(h, 0);
   {
     Timed tm(h, KK_PCG_PRE);
-    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->z64, h->part);
+    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->part);
   }
   HIPCHK(hipGetLastError());
   if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;
@@ -681,8 +680,9 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
   for (int j = 1; j <= max_it; ++j) {
     {
       Timed tm(h, KK_PCG_DIR);
-      launch_pcg_dir(h->stream, k, h->diag64, cf, h->z64, p_in, p_out, h->q64, beta, j == 1,
-                     h->part);
+      // z = sigma_b * (V-cycle output): sigma_b is still the scale of that V-cycle's input
+      launch_pcg_dir<T>(h->stream, k, h->diag64, cf, L[0].x, sigma_b, p_in, p_out, h->q64, beta,
+                        j == 1, h->part);
     }
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, slot_bit(RS_PQ))) != RH_OK) return st;
@@ -710,7 +710,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     vcycle<T>(h, 0);
     {
       Timed tm(h, KK_PCG_PRE);
-      launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->z64, h->part);
+      launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->part);
     }
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;

@@ -142,11 +142,13 @@ bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles);
 template <class T>
 void launch_mg_residual(hipStream_t s, const LevelK<T>& l);
 // r = b - A x on f fused with the restriction of r into c.b (f.r is not
-// written); returns false (nothing launched) unless rbgs_march_fits(f,
-// min_tiles) and f has even dimensions.
+// written); returns false (nothing launched) unless resid_restrict_fits(f,
+// min_tiles): even dimensions and enough of its tiles.
 template <class T>
 bool launch_resid_restrict_march(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c,
                                  long long min_tiles);
+template <class T>
+bool resid_restrict_fits(const LevelK<T>& f, long long min_tiles);
 template <class T>
 void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
 template <class T>
@@ -165,16 +167,19 @@ template <class T>
 void launch_accum_defect(hipStream_t s, const StepK& k, const DefectArgs& a, const T* x, T* b,
                          double* part);
 
+// p_out = z + beta p_in (z = sigma zT; p_out = z when first), q = S p_out and
+// the partial sums of p_out . q
+template <class T>
 void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
-                    const double* z, const double* p_in, double* p_out, double* q, double beta,
-                    int first, double* part);
+                    const T* zT, double sigma, const double* p_in, double* p_out, double* q,
+                    double beta, int first, double* part);
 template <class T>
 void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double* p,
                        const double* q, double* x, double* r, double inv_sigma, T* b, int first,
                        double* part);
 template <class T>
 void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
-                        const double* q, double* z, double* part);
+                        const double* q, double* part);
 
 // adjoint step
 struct AdjArgs {

@@ -733,35 +733,59 @@ void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, in
 // next plane's values are fetched into registers one iteration ahead and
 // stored to LDS after the current plane's updates.  Each thread updates
 // fixed z-pairs (lz, lz+1): exactly one cell of a pair has the colour.
+// Tile shapes (rows x z-columns, threads): the sweep and the fused residual
+// use the same staging; measured on 512^3 the sweep is fastest on 16 x 64
+// tiles of 512 threads and the residual on 8 x 64 tiles of 256 (FP32).
 template <class T>
 struct MarchTile;
 template <>
 struct MarchTile<float> {
-  static constexpr int TY = 8, TZ = 64;
+  static constexpr int TY = 16, TZ = 64, NT = 512;
 };
 template <>
 struct MarchTile<double> {
-  static constexpr int TY = 8, TZ = 32;
+  static constexpr int TY = 8, TZ = 32, NT = 256;
+};
+template <class T>
+struct ResidTile;
+template <>
+struct ResidTile<float> {
+  static constexpr int TY = 8, TZ = 64, NT = 256;
+};
+template <>
+struct ResidTile<double> {
+  static constexpr int TY = 8, TZ = 32, NT = 256;
 };
 
 __device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-template <class T, int TY, int TZ, int FINE>
-__global__ void __launch_bounds__(kBlock)
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Give each XCD a contiguous range of tile indices, so tiles that share
+// halo cache lines (neighbours along z come next in tile order) run on the
+// same XCD at about the same time.  A bijection of [0, nb).
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int bid, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int xcd = bid % kXcds, k = bid / kXcds;
+  return xcd * q + min(xcd, r) + k;
+}
+
+template <class T, int TY, int TZ, int NT, int FINE>
+__global__ void __launch_bounds__(NT)
 k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
   static_assert(TZ % 2 == 0, "z-pairs need an even tile width");
   constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
   constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
   constexpr int CP = CR * HZ;                               // coefficient plane (row stride HZ)
-  constexpr int NLX = (PL + kBlock - 1) / kBlock;
-  constexpr int NLC = (CN + kBlock - 1) / kBlock;
-  constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + kBlock - 1) / kBlock;
-  constexpr int NBLK = (TY * TZ / 2 + kBlock - 1) / kBlock;
+  constexpr int NLX = (PL + NT - 1) / NT;
+  constexpr int NLC = (CN + NT - 1) / NT;
+  constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + NT - 1) / NT;
+  constexpr int NBLK = (TY * TZ / 2 + NT - 1) / NT;
   __shared__ T xs[4 * PL];
   __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes p-1, p)
   __shared__ T c0s[3 * CP];    // x faces (planes p-2, p-1, p)
   const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
-  int bid = blockIdx.x;
+  int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tz = bid % ntz;
   bid /= ntz;
   const int ty = bid % nty;
@@ -783,12 +807,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
   int xoff[NLX], coff[NLC];
 #pragma unroll
   for (int j = 0; j < NLX; ++j) {
-    const int t = tid + j * kBlock;
+    const int t = tid + j * NT;
     xoff[j] = t < PL ? inplane(t / HZ, t % HZ) : -1;
   }
 #pragma unroll
   for (int j = 0; j < NLC; ++j) {
-    const int t = tid + j * kBlock;
+    const int t = tid + j * NT;
     coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
   }
   struct Buf {
@@ -805,7 +829,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
     T* dst = xs + pmod(p, 4) * PL;
 #pragma unroll
     for (int j = 0; j < NLX; ++j) {
-      const int t = tid + j * kBlock;
+      const int t = tid + j * NT;
       if (t < PL) dst[t] = B.x[j];
     }
   };
@@ -828,7 +852,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
     const int s2 = pmod(p, 2) * CP, s3 = pmod(p, 3) * CP;
 #pragma unroll
     for (int j = 0; j < NLC; ++j) {
-      const int t = tid + j * kBlock;
+      const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
       c0s[s3 + li] = B.c[4][j];
@@ -858,7 +882,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
     T nv[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      const int t = tid + j * kBlock;
+      const int t = tid + j * NT;
       qs[j] = -1;
       if (t >= ey * half) continue;
       const int ly = lo + t / half;
@@ -908,7 +932,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
       update(std::integral_constant<int, NBLK>(), q, 1 - first_color, 2, TY, TZ);
       __syncthreads();
       const T* src = xs + pmod(q, 4) * PL;
-      for (int t = tid; t < TY * TZ; t += kBlock) {
+      for (int t = tid; t < TY * TZ; t += NT) {
         const int lz = t % TZ, ly = t / TZ;
         const int gy = ty * TY + ly, gz = tz * TZ + lz;
         if (gy < l.ny && gz < l.nz) l.x2[q * plane + gy * l.nz + gz] = src[(ly + 2) * HZ + lz + 2];
@@ -929,14 +953,18 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
 // x planes per block of the marching sweep: 32, or fewer (down to 8) when
 // that is what it takes to reach min_tiles workgroups; 0 when the level does
 // not fit the tiles (the caller then sweeps colour by colour).
-template <class T>
-int march_chunk(const LevelK<T>& l, long long min_tiles) {
-  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
+template <class T, int TY, int TZ>
+int march_chunk_for(const LevelK<T>& l, long long min_tiles) {
   if (!l.x2 || l.nz < TZ || l.ny < TY || l.nx < 4 || l.N >= (1LL << 31)) return 0;
   const long long tiles = (long long)((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ);
   for (int xc = 32; xc >= 8; xc /= 2)
     if (tiles * ((l.nx + xc - 1) / xc) >= min_tiles) return xc;
   return 0;
+}
+
+template <class T>
+int march_chunk(const LevelK<T>& l, long long min_tiles) {
+  return march_chunk_for<T, MarchTile<T>::TY, MarchTile<T>::TZ>(l, min_tiles);
 }
 
 template <class T>
@@ -951,11 +979,12 @@ bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int z
   const int xc = march_chunk(l, min_tiles);
   if (xc == 0) return false;
   const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + xc - 1) / xc);
+  constexpr int NT = MarchTile<T>::NT;
   if (fine)
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, 1>), dim3(nb), dim3(kBlock), 0, s, l,
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 1>), dim3(nb), dim3(NT), 0, s, l,
                        first_color, zero_init, xc);
   else
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, 0>), dim3(nb), dim3(kBlock), 0, s, l,
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 0>), dim3(nb), dim3(NT), 0, s, l,
                        first_color, zero_init, xc);
   return true;
 }
@@ -1025,25 +1054,25 @@ void launch_restrict(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
 // running sum; a coarse plane is written once its fourth fine plane is in.
 // Restriction reads fold the stencil at non-periodic walls (the fine plane,
 // row or column 0 stands for -1, and n-1 for n); one barrier per plane.
-template <class T, int TY, int TZ>
-__global__ void __launch_bounds__(kBlock)
+template <class T, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT)
 k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
   static_assert(TZ % 2 == 0 && TY % 2 == 0, "tiles hold whole coarse cells");
   constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
   constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
   constexpr int CP = CR * HZ;
-  constexpr int NLX = (PL + kBlock - 1) / kBlock;
-  constexpr int NLC = (CN + kBlock - 1) / kBlock;
+  constexpr int NLX = (PL + NT - 1) / NT;
+  constexpr int NLC = (CN + NT - 1) / NT;
   constexpr int RR = TY + 2, RZ = TZ + 2, RN = RR * RZ;   // residual slots: rows/cols 1..
-  constexpr int NRES = (RN + kBlock - 1) / kBlock;
+  constexpr int NRES = (RN + NT - 1) / NT;
   constexpr int NCC = (TY / 2) * (TZ / 2);                 // coarse cells per tile
-  static_assert(NCC <= kBlock, "one coarse cell per thread");
+  static_assert(NCC <= NT, "one coarse cell per thread");
   __shared__ T xs[4 * PL];
   __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes i, i+1)
   __shared__ T c0s[3 * CP];    // x faces (planes i-1, i, i+1)
   __shared__ T rs[2][CP];      // residual planes (same coordinates)
   const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
-  int bid = blockIdx.x;
+  int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tz = bid % ntz;
   bid /= ntz;
   const int ty = bid % nty;
@@ -1065,19 +1094,19 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
   int xoff[NLX], coff[NLC];
 #pragma unroll
   for (int j = 0; j < NLX; ++j) {
-    const int t = tid + j * kBlock;
+    const int t = tid + j * NT;
     xoff[j] = t < PL ? inplane(t / HZ, t % HZ) : -1;
   }
 #pragma unroll
   for (int j = 0; j < NLC; ++j) {
-    const int t = tid + j * kBlock;
+    const int t = tid + j * NT;
     coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
   }
   // residual slots of this thread (LDS index, or -1 when outside the grid)
   int rq[NRES];
 #pragma unroll
   for (int j = 0; j < NRES; ++j) {
-    const int t = tid + j * kBlock;
+    const int t = tid + j * NT;
     rq[j] = -1;
     if (t < RN) {
       const int ly = 1 + t / RZ, lz = 1 + t % RZ;
@@ -1110,7 +1139,7 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     T* dst = xs + pmod(p, 4) * PL;
 #pragma unroll
     for (int j = 0; j < NLX; ++j) {
-      const int t = tid + j * kBlock;
+      const int t = tid + j * NT;
       if (t < PL) dst[t] = B.x[j];
     }
   };
@@ -1133,7 +1162,7 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     const int s2 = pmod(p, 2) * CP, s3 = pmod(p, 3) * CP;
 #pragma unroll
     for (int j = 0; j < NLC; ++j) {
-      const int t = tid + j * kBlock;
+      const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
       c0s[s3 + li] = B.c[4][j];
@@ -1233,13 +1262,20 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
 }
 
 template <class T>
+bool resid_restrict_fits(const LevelK<T>& f, long long min_tiles) {
+  return (f.nx % 2 == 0 && f.ny % 2 == 0 && f.nz % 2 == 0) &&
+         march_chunk_for<T, ResidTile<T>::TY, ResidTile<T>::TZ>(f, min_tiles) > 0;
+}
+
+template <class T>
 bool launch_resid_restrict_march(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c,
                                  long long min_tiles) {
-  constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
-  const int xc = march_chunk(f, min_tiles);
-  if (xc == 0 || f.nx % 2 || f.ny % 2 || f.nz % 2) return false;
+  constexpr int TY = ResidTile<T>::TY, TZ = ResidTile<T>::TZ;
+  if (!resid_restrict_fits(f, min_tiles)) return false;
+  const int xc = march_chunk_for<T, TY, TZ>(f, min_tiles);
   const int nb = ((f.ny + TY - 1) / TY) * ((f.nz + TZ - 1) / TZ) * ((f.nx + xc - 1) / xc);
-  hipLaunchKernelGGL((k_resid_restrict_march<T, TY, TZ>), dim3(nb), dim3(kBlock), 0, s, f, c, xc);
+  constexpr int NT = ResidTile<T>::NT;
+  hipLaunchKernelGGL((k_resid_restrict_march<T, TY, TZ, NT>), dim3(nb), dim3(NT), 0, s, f, c, xc);
   return true;
 }
 
@@ -1348,11 +1384,13 @@ void launch_accum_defect(hipStream_t s, const StepK& k, const DefectArgs& a, con
 // flexible preconditioned conjugate gradients in FP64 (V-cycle preconditioner)
 // ---------------------------------------------------------------------------
 // A: p = z + beta p (p = z when first);  q = S p;  partial p.q
+template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ cfx,
           const double* __restrict__ cfy, const double* __restrict__ cfz,
-          const double* __restrict__ z, const double* __restrict__ p_in, double* __restrict__ p_out,
-          double* __restrict__ q, double beta, int first, double* __restrict__ part) {
+          const T* __restrict__ zT, double sigma, const double* __restrict__ p_in,
+          double* __restrict__ p_out, double* __restrict__ q, double beta, int first,
+          double* __restrict__ part) {
   const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
                       k.bc[4] == RH_BC_PERIODIC};
   const int nd[3] = {k.nx, k.ny, k.nz};
@@ -1362,18 +1400,21 @@ k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ c
        idx += (long long)blockDim.x * gridDim.x) {
     int c[3];
     cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
-    const double pP = first ? z[idx] : z[idx] + beta * p_in[idx];
+    const double zP = sigma * (double)zT[idx];
+    const double pP = first ? zP : zP + beta * p_in[idx];
     double off = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int qq[3];
       if (neighbour(c, nd, per, d, +1, qq)) {
         const long long Q = cell_index(qq[0], qq[1], qq[2], k.ny, k.nz);
-        off += cf[d][idx] * (first ? z[Q] : z[Q] + beta * p_in[Q]);
+        const double zQ = sigma * (double)zT[Q];
+        off += cf[d][idx] * (first ? zQ : zQ + beta * p_in[Q]);
       }
       if (neighbour(c, nd, per, d, -1, qq)) {
         const long long Q = cell_index(qq[0], qq[1], qq[2], k.ny, k.nz);
-        off += cf[d][Q] * (first ? z[Q] : z[Q] + beta * p_in[Q]);
+        const double zQ = sigma * (double)zT[Q];
+        off += cf[d][Q] * (first ? zQ : zQ + beta * p_in[Q]);
       }
     }
     const double qP = diag[idx] * pP - off;
@@ -1397,10 +1438,11 @@ k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ c
 // in the order of k_pcg_dir (+x, -x, +y, -y, +z, -z).
 constexpr int kDirTY = 8, kDirTZ = 64, kDirXC = 32;
 
+template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restrict__ cfx,
                 const double* __restrict__ cfy, const double* __restrict__ cfz,
-                const double* __restrict__ z, const double* __restrict__ p_in,
+                const T* __restrict__ zT, double sigma, const double* __restrict__ p_in,
                 double* __restrict__ p_out, double* __restrict__ q, double beta, int first, int xc,
                 double* __restrict__ part) {
   constexpr int TY = kDirTY, TZ = kDirTZ, HZ = TZ + 2, PL = (TY + 2) * HZ;
@@ -1411,7 +1453,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
   const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
                       k.bc[4] == RH_BC_PERIODIC};
   const int ntz = (k.nz + TZ - 1) / TZ, nty = (k.ny + TY - 1) / TY;
-  int bid = blockIdx.x;
+  int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tz = bid % ntz;
   bid /= ntz;
   const int ty = bid % nty;
@@ -1464,7 +1506,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
     pv = 0.0;
     if (gx < 0 || off < 0) return;
     const int P = gx * plane + off;
-    zv = z[P];
+    zv = sigma * (double)zT[P];
     if (!first) pv = p_in[P];
   };
   auto form = [&](double zv, double pv) { return first ? zv : zv + beta * pv; };
@@ -1570,9 +1612,10 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
   block_reduce_store<1>(v, im, sl, part);
 }
 
+template <class T>
 void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
-                    const double* z, const double* p_in, double* p_out, double* q, double beta,
-                    int first, double* part) {
+                    const T* zT, double sigma, const double* p_in, double* p_out, double* q,
+                    double beta, int first, double* part) {
   const int nty = (k.ny + kDirTY - 1) / kDirTY, ntz = (k.nz + kDirTZ - 1) / kDirTZ;
   const long long tiles = (long long)nty * ntz;
   if (k.nz >= kDirTZ && k.ny >= kDirTY && k.nx >= 2 && k.N < (1LL << 31) && tiles <= kPartCap) {
@@ -1580,12 +1623,12 @@ void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const dou
     if (tiles * ncx > kPartCap) ncx = (int)(kPartCap / tiles);
     const int xc = (k.nx + ncx - 1) / ncx;
     ncx = (k.nx + xc - 1) / xc;
-    hipLaunchKernelGGL(k_pcg_dir_march, dim3((unsigned)(tiles * ncx)), dim3(kBlock), 0, s, k,
-                       diag, cf[0], cf[1], cf[2], z, p_in, p_out, q, beta, first, xc, part);
+    hipLaunchKernelGGL((k_pcg_dir_march<T>), dim3((unsigned)(tiles * ncx)), dim3(kBlock), 0, s, k,
+                       diag, cf[0], cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, xc, part);
     return;
   }
-  hipLaunchKernelGGL(k_pcg_dir, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, diag, cf[0], cf[1],
-                     cf[2], z, p_in, p_out, q, beta, first, part);
+  hipLaunchKernelGGL((k_pcg_dir<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, diag, cf[0],
+                     cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, part);
 }
 
 // B: x += alpha p;  r -= alpha q;  norms of r;  b = r * inv_sigma (preconditioner input)
@@ -1619,16 +1662,16 @@ void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double
                      x, r, inv_sigma, b, first, part);
 }
 
-// C: z = sigma * zT;  partial z.r and z.q (q may be null on the first pass)
+// C: partial z.r and z.q for z = sigma * zT (q may be null on the first pass);
+// z itself is formed again where it is used (the direction kernel)
 template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_pcg_precond(StepK k, double sigma, const T* __restrict__ zT, const double* __restrict__ r,
-              const double* __restrict__ q, double* __restrict__ z, double* __restrict__ part) {
+              const double* __restrict__ q, double* __restrict__ part) {
   double zr = 0.0, zq = 0.0;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
        idx += (long long)blockDim.x * gridDim.x) {
     const double zv = sigma * (double)zT[idx];
-    z[idx] = zv;
     zr += zv * r[idx];
     if (q) zq += zv * q[idx];
   }
@@ -1640,9 +1683,9 @@ k_pcg_precond(StepK k, double sigma, const T* __restrict__ zT, const double* __r
 
 template <class T>
 void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
-                        const double* q, double* z, double* part) {
+                        const double* q, double* part) {
   hipLaunchKernelGGL((k_pcg_precond<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, sigma, zT, r,
-                     q, z, part);
+                     q, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1922,6 +1965,7 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
   template bool rbgs_march_fits<T>(const LevelK<T>&, long long);                             \
   template bool launch_resid_restrict_march<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&, \
                                                long long);                                    \
+  template bool resid_restrict_fits<T>(const LevelK<T>&, long long);                         \
   template void launch_mg_residual<T>(hipStream_t, const LevelK<T>&);                         \
   template void launch_restrict<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);          \
   template void launch_prolong<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&);           \
@@ -1932,7 +1976,10 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
                                      const double*, double*, double*, double, T*, int,        \
                                      double*);                                                \
   template void launch_pcg_precond<T>(hipStream_t, const StepK&, double, const T*,            \
-                                      const double*, const double*, double*, double*);
+                                      const double*, const double*, double*);                 \
+  template void launch_pcg_dir<T>(hipStream_t, const StepK&, const double*,                   \
+                                  const double* const[3], const T*, double, const double*,    \
+                                  double*, double*, double, int, double*);
 RH_INST(float)
 RH_INST(double)
 template void launch_coarsen_faces<double, double>(hipStream_t, int, int, int,

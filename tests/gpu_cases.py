@@ -15,7 +15,8 @@ CASES = {
         "bc": (W.BC_ZEROFLUX, W.BC_OUTFLOW) * 3, "sources": "corner"}),
     "theta06_smalldt": (2, (16, 16, 16), {"theta": 0.6, "dt_Myr": 0.02}),
     # tall grids: with smoother=2 the finest level runs the fused marching
-    # sweep (its tiles need nz >= 64 in FP32, >= 32 in FP64, ny >= 8, nx >= 4)
+    # sweep (its tiles need nz >= 64 and ny >= 16 in FP32, nz >= 32 and ny >= 8 in
+    # FP64, nx >= 4)
     "lognormal_tall": (2, (8, 16, 64), {"n_sources": 6}),
     "stromgren_tall": (0, (8, 16, 64), {}),
 }
