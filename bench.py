@@ -35,12 +35,14 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
         # one colour of a sweep: other-colour x, own b and diag, all three
         # + face arrays (own + faces and the neighbours' - faces), own x written
         "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
-        "mg_residual_fine": 6 * T + T,
+        # residual fused with the restriction (x, b, diag, 3 faces in; coarse
+        # right-hand side out), as the benchmark sizes run it
+        "mg_residual_fine": 6 * T + T / 8,
         "restrict_fine": T + T / 8,
         "prolong_fine": T / 8 + 2 * T,
-        "pcg_direction": 8 * 8,             # z, p, diag, 3 cf in; p, q out
+        "pcg_direction": T + 7 * 8,         # zT, p, diag, 3 cf in; p, q out
         "pcg_update": 6 * 8 + T,            # p, q, x, r in; x, r out; b out
-        "pcg_precond": T + 3 * 8,           # zT, r, q in; z out
+        "pcg_precond": T + 2 * 8,           # zT, r, q in (dot products only)
         "residual_schur": 8 * 8 + 2 * 8 + (T if T == 4 else 0),
         "local_solve": (12 if not iso else 8) * 8 + (7 if not iso else 4) * 8,
         "step_setup": 3 * 8 + 3 * 8 + (3 * 4 if T == 4 else 0) + 8,
