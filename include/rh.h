@@ -118,6 +118,18 @@ typedef struct rh_step_stats {
                                /* 3 coarse setup, 4 V-cycles, 5 defect/accumulate        */
 } rh_step_stats;
 
+/* Statistics of rh_advance (host memory). */
+typedef struct rh_advance_stats {
+  int32_t steps;               /* accepted implicit steps                                */
+  int32_t rejected;            /* rejected attempts (failed step or negative E)          */
+  int32_t newton_its;          /* Newton iterations over the accepted steps              */
+  int32_t lin_its_total;       /* V-cycles over the accepted steps                       */
+  double dt_min, dt_max;       /* smallest / largest accepted step (s)                   */
+  double dt_next;              /* step the controller proposes for the next call (s)     */
+  double change_max;           /* largest weighted change of an accepted step            */
+  double change_last;          /* weighted change of the last accepted step              */
+} rh_advance_stats;
+
 typedef struct rh_handle rh_handle;
 
 /* Fill p with the defaults (a 16^3 static zero-flux grid; every solver
@@ -157,6 +169,27 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n_s, double dt_s, const double*
                           const double* nHI_n, const double* E_1, const double* e_1,
                           const double* nHI_1, double* lE, double* le, double* lnHI,
                           double* g_src, double* g_nH, rh_step_stats* stats);
+
+/* Advance (E, e, nHI) in place from t0 to t_end with implicit steps whose
+ * size follows the temporal accuracy tau_tol (Verification section: the
+ * solver settings name tau_tol next to theta and the norm exponent p = 2;
+ * the controller itself is given in the method's companion paper, this is
+ * its reading): after an accepted step the weighted RMS change
+ *   w = sqrt(sum_P [(dE/E_s)^2 + (de/e^n)^2 + (dn_HI/n_H)^2] / (N nvars)),
+ * with the weights of the Newton norm (equation rmsnorm, E_s as there), sets
+ * the next step dt * clamp(tau_tol / w, 0.1, 2), capped by dt_max_s and
+ * shortened to land on t_end.  An attempt is rejected and retried with half
+ * the step when rh_implicit_step fails (RH_ENEWTON, RH_ELINEAR,
+ * RH_ENONFINITE) or when some E^{n+1} < -1e-10 E_s (positivity safeguard for
+ * theta < 1: the explicit part can flip the sign of E in optically thick
+ * cells); a rejected attempt leaves the state at U^n.  dt0_s is the first
+ * attempted step.  Returns RH_OK on reaching t_end; otherwise the status of
+ * the last failed attempt after 12 consecutive rejections (state at the last
+ * accepted time, reported by *t_reached).  stats and t_reached may be NULL.
+ * Device fields as for rh_implicit_step. */
+rh_status rh_advance(rh_handle* h, double t0_s, double t_end_s, double dt0_s, double tau_tol,
+                     double dt_max_s, const double* nH, const double* src, double* E, double* e,
+                     double* nHI, rh_advance_stats* stats, double* t_reached);
 
 /* Evaluate the residual f(U) of the step from U^n = (E_n, e_n, nHI_n) at
  * the state U = (E, e, nHI), exactly as rh_implicit_step does (face limiter

@@ -23,10 +23,11 @@ Modules:
   adjoint     adjoint of the step (implicit-function theorem, sparse transposes)
   analytic    Stromgren radius and the Shapiro-Giroux I-front law
   diagnostics I-front radius, budgets
+  controller  adaptive time steps with the temporal accuracy tau_tol
 
 Parity status of each function is stated in its module header.
 """
 from .constants import *  # noqa: F401,F403
-from . import grey, cosmology, rates, model, newton, adjoint, analytic, diagnostics  # noqa: F401
+from . import grey, cosmology, rates, model, newton, adjoint, analytic, diagnostics, controller  # noqa: F401
 from .model import Params, StepContext, params_from_workload, initial_state, source_field  # noqa: F401
 from .newton import step, run  # noqa: F401

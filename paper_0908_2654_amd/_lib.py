@@ -57,6 +57,17 @@ class RhStepStats(ctypes.Structure):
         return d
 
 
+class RhAdvanceStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", _i32), ("rejected", _i32), ("newton_its", _i32), ("lin_its_total", _i32),
+        ("dt_min", _f64), ("dt_max", _f64), ("dt_next", _f64), ("change_max", _f64),
+        ("change_last", _f64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported symbols and their signatures (name -> (restype, argtypes))
 _PP = ctypes.POINTER(RhParams)
 _SP = ctypes.POINTER(RhStepStats)
@@ -67,6 +78,8 @@ SIGNATURES = {
     "rh_implicit_step": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _SP]),
     "rh_adjoint_step": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _vp, _vp, _vp, _vp, _SP]),
+    "rh_advance": (_i32, [_vp, _f64, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp, _vp,
+                          ctypes.POINTER(RhAdvanceStats), ctypes.POINTER(_f64)]),
     "rh_residual": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, ctypes.POINTER(_f64)]),
     "rh_schur_solve": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

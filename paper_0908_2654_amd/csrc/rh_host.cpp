@@ -247,6 +247,7 @@ struct rh_handle {
   std::string err;
   // statistics of the current call
   int lin_its, local_its_max;
+  double last_E_s = 1.0;  // E_s of the last step set up (weight of E in the norms)
   double lin_res_max;
 };
 
@@ -427,6 +428,7 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
   if (st != RH_OK) return st;
   if (h->hred[RS_NONFINITE] != 0.0) return fail(h, RH_ENONFINITE, "non-finite E^n, n_HI^n or src");
   k.E_s = std::max(std::max(h->hred[RS_EMAX], k.dt * h->hred[RS_SMAX]), h->p.E_floor);
+  h->last_E_s = k.E_s;
   // coarse face coefficients
   for (int l = 1; l < h->plan.nlev; ++l) {
     const int* fd = h->plan.dims[l - 1];
@@ -950,6 +952,75 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     stats->t_ms[0] = ms;
   }
   return result;
+}
+
+rh_status rh_advance(rh_handle* h, double t0, double t_end, double dt0, double tau_tol,
+                     double dt_max, const double* nH, const double* src, double* E, double* e,
+                     double* nHI, rh_advance_stats* stats, double* t_reached) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (t_reached) *t_reached = t0;
+  if (!std::isfinite(t0) || !std::isfinite(t_end) || !(t_end > t0) || !(dt0 > 0) ||
+      !(tau_tol > 0) || !(dt_max > 0))
+    return fail(h, RH_EINVAL, "need t_end > t0 and dt0, tau_tol, dt_max > 0");
+  const double eps_t = 1e-12 * std::max(std::fabs(t_end), t_end - t0);
+  constexpr int kMaxRejects = 12;
+  double t = t0, dt = std::min(dt0, dt_max);
+  double dt_min_acc = INFINITY, dt_max_acc = 0.0;
+  int rejects = 0;
+  rh_advance_stats acc{};
+  while (t_end - t > eps_t) {
+    const bool last = dt >= t_end - t - eps_t;
+    const double dt_try = last ? t_end - t : dt;
+    rh_step_stats ss{};
+    rh_status why = rh_implicit_step(h, t, dt_try, nH, src, E, e, nHI, &ss);
+    if (why != RH_OK && why != RH_ENEWTON && why != RH_ELINEAR && why != RH_ENONFINITE)
+      return why;  // invalid arguments or a HIP error: no retry
+    double w = 0.0;
+    if (why == RH_OK) {
+      // h->En / en / nn still hold U^n of this step
+      launch_change_norm(h->stream, h->N, h->last_E_s, E, iso ? nullptr : e, nHI, h->En,
+                         iso ? nullptr : h->en, h->nn, nH, h->part);
+      HIPCHK(hipGetLastError());
+      rh_status st = sync_reductions(h, slot_bit(RS_CHG2) | slot_bit(RS_NEGE));
+      if (st != RH_OK) return st;
+      w = std::sqrt(h->hred[RS_CHG2] / (h->N * nvars(h)));
+      if (h->hred[RS_NEGE] > 1e-10 || !std::isfinite(w)) {
+        // negative E (or a non-finite change): back to U^n
+        if ((st = copy_state(h, E, e, nHI, h->En, h->en, h->nn)) != RH_OK) return st;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        why = RH_ENONFINITE;
+      }
+    }
+    if (why != RH_OK) {
+      ++acc.rejected;
+      if (++rejects >= kMaxRejects) {
+        if (stats) *stats = acc;
+        if (t_reached) *t_reached = t;
+        return fail(h, why, "rh_advance: step rejected 12 times in a row");
+      }
+      dt = 0.5 * dt_try;
+      continue;
+    }
+    rejects = 0;
+    t = last ? t_end : t + dt_try;
+    ++acc.steps;
+    acc.newton_its += ss.newton_its;
+    acc.lin_its_total += ss.lin_its_total;
+    dt_min_acc = std::min(dt_min_acc, dt_try);
+    dt_max_acc = std::max(dt_max_acc, dt_try);
+    acc.change_max = std::max(acc.change_max, w);
+    acc.change_last = w;
+    const double factor = w > 0.0 ? std::min(2.0, std::max(0.1, tau_tol / w)) : 2.0;
+    dt = std::min(dt_try * factor, dt_max);
+  }
+  acc.dt_min = dt_min_acc;
+  acc.dt_max = dt_max_acc;
+  acc.dt_next = dt;
+  if (stats) *stats = acc;
+  if (t_reached) *t_reached = t;
+  return RH_OK;
 }
 
 rh_status rh_residual(rh_handle* h, double t_n, double dt, const double* nH, const double* src,

@@ -77,6 +77,8 @@ enum RedSlot {
   RS_PQ,           // sum p.q   (conjugate gradients)
   RS_ZR,           // sum z.r
   RS_ZQ,           // sum z.q
+  RS_CHG2,         // sum of squared weighted changes U^{n+1} - U^n (step controller)
+  RS_NEGE,         // max over cells of -E/E_s (positivity check)
   RS_COUNT
 };
 static_assert(RS_COUNT <= 32, "slot masks are 32-bit");
@@ -85,6 +87,12 @@ constexpr unsigned slot_bit(int s) { return 1u << s; }
 
 
 // ---- launchers (rh_kernels.hip) ------------------------------------------
+// Weighted change of a step and its most negative E: partial sums of
+// (dE/E_s)^2 + (de/e^n)^2 + (dn/n_H)^2 (RS_CHG2; no e term when e is null)
+// and max(-E/E_s) (RS_NEGE).
+void launch_change_norm(hipStream_t s, long long N, double E_s, const double* E, const double* e,
+                        const double* n, const double* En, const double* en, const double* nn,
+                        const double* nH, double* part);
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
                        float* cf32_x, float* cf32_y, float* cf32_z, double* rhsn,

@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   const int s = blockIdx.x;
   if (!((mask >> s) & 1u)) return;
   const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS || s == RS_EMAX ||
-                       s == RS_SMAX || s == RS_NONFINITE || s == RS_BAD_RES);
+                       s == RS_SMAX || s == RS_NONFINITE || s == RS_BAD_RES || s == RS_NEGE);
   const int nblocks =
       (int)fmin(fmax(part[(long long)RS_COUNT * kPartCap + s], 0.0), (double)kPartCap);
   double v = is_max ? -INFINITY : 0.0;
@@ -508,6 +508,36 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
     for (int w = 1; w < kBlock / 64; ++w) t = is_max ? fmax(t, sh[w]) : t + sh[w];
     out[s] = t;
   }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_change_norm(long long N, double E_s, const double* __restrict__ E, const double* __restrict__ e,
+              const double* __restrict__ n, const double* __restrict__ En,
+              const double* __restrict__ en, const double* __restrict__ nn,
+              const double* __restrict__ nH, double* __restrict__ part) {
+  double s2 = 0.0, neg = -INFINITY;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    const double dE = (E[idx] - En[idx]) / E_s;
+    const double dn = (n[idx] - nn[idx]) / nH[idx];
+    s2 += dE * dE + dn * dn;
+    if (e) {
+      const double de = (e[idx] - en[idx]) / en[idx];
+      s2 += de * de;
+    }
+    neg = fmax(neg, -E[idx] / E_s);
+  }
+  double v[2] = {s2, neg};
+  const int im[2] = {0, 1};
+  const int sl[2] = {RS_CHG2, RS_NEGE};
+  block_reduce_store<2>(v, im, sl, part);
+}
+
+void launch_change_norm(hipStream_t s, long long N, double E_s, const double* E, const double* e,
+                        const double* n, const double* En, const double* en, const double* nn,
+                        const double* nH, double* part) {
+  hipLaunchKernelGGL(k_change_norm, dim3(red_grid(N)), dim3(kBlock), 0, s, N, E_s, E, e, n, En,
+                     en, nn, nH, part);
 }
 
 void launch_finalize(hipStream_t s, const double* part, double* out, unsigned mask) {

@@ -10,7 +10,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import RhParams, RhStepStats, check, lib
+from ._lib import RhAdvanceStats, RhParams, RhStepStats, check, lib
 
 _F64 = ctypes.c_double
 
@@ -137,6 +137,19 @@ class Solver:
                                  _ptr(e), _ptr(nHI), ctypes.byref(st))
         check(s, self._h)
         return st.as_dict()
+
+    def advance(self, t0, t_end, dt0, tau_tol, dt_max, nH, src, E, e, nHI) -> dict:
+        """Adaptive steps from t0 to t_end in place on (E, e, nHI); returns the
+        controller statistics plus t_reached.  Raises RhError if it stops early."""
+        st = RhAdvanceStats()
+        tr = _F64()
+        s = lib.rh_advance(self._h, float(t0), float(t_end), float(dt0), float(tau_tol),
+                           float(dt_max), _ptr(nH), _ptr(src), _ptr(E), _ptr(e), _ptr(nHI),
+                           ctypes.byref(st), ctypes.byref(tr))
+        check(s, self._h)
+        d = st.as_dict()
+        d["t_reached"] = tr.value
+        return d
 
     def residual(self, t, dt, nH, src, Un, U, want_fields=True):
         """f(U) of the step from U^n: returns (fE, fe, fn, norm)."""
