@@ -60,7 +60,11 @@ enum { RH_BC_ZEROFLUX = 0, RH_BC_PERIODIC = 1, RH_BC_OUTFLOW = 2 };
 enum { RH_SPEC_MONO = 0, RH_SPEC_BLACKBODY = 1 };
 enum { RH_RATES_CONST = 0, RH_RATES_FIT = 1 };
 enum { RH_COOL_RECB = 1, RH_COOL_COLLEXC = 2, RH_COOL_COMPTON = 4 };
-enum { RH_COSMO_STATIC = 0, RH_COSMO_EDS = 1, RH_COSMO_FLAT_LCDM = 2 };
+/* Expansion laws (Physical Model section; Friedmann equation): static a = 1;
+ * Einstein-de Sitter (Omega_m = 1); flat LCDM (Omega_m + Omega_L = 1); open
+ * (Omega_L = 0, 0 < Omega_m < 1: the q0 = Omega_m / 2 = 0.05 rows of the
+ * verification section's table). */
+enum { RH_COSMO_STATIC = 0, RH_COSMO_EDS = 1, RH_COSMO_FLAT_LCDM = 2, RH_COSMO_OPEN = 3 };
 enum { RH_PREC_FP64 = 0, RH_PREC_MIXED = 1 };
 
 /* Problem and solver parameters (plain data, validated by rh_setup). */

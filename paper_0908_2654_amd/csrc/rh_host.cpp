@@ -91,6 +91,33 @@ Grey grey_constants(const rh_params& p) {
 // ---------------------------------------------------------------------------
 // cosmology (Friedmann equation closed forms)
 // ---------------------------------------------------------------------------
+// Open universe (Omega_L = 0, Ok = 1 - Omega_m > 0): H^2 = H0^2 (Om a^-3 +
+// Ok a^-2) is solved by a = A (cosh u - 1), t = B (sinh u - u) with
+// A = Om / (2 Ok), B = Om / (2 H0 Ok^1.5).  g(u) = sinh u - u, written as a
+// series where the difference would cancel.
+static double open_g(double u) {
+  if (u < 0.1) {
+    const double u2 = u * u;
+    return u * u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0 * (1.0 + u2 / 72.0)));
+  }
+  return std::sinh(u) - u;
+}
+
+// The development angle u with g(u) = tau: Newton from above (g is convex
+// and increasing for u > 0, so the iterates decrease monotonically to the root).
+static double open_angle(double tau) {
+  double u = std::max(std::cbrt(6.0 * tau), std::asinh(tau) + 1.0);
+  while (open_g(u) < tau) u *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    const double gp = 2.0 * std::sinh(0.5 * u) * std::sinh(0.5 * u);  // cosh u - 1
+    const double step = (open_g(u) - tau) / gp;
+    if (!(step > 0.0)) break;
+    u -= step;
+    if (step <= 1e-16 * u) break;
+  }
+  return u;
+}
+
 void cosmo_at(const rh_params& p, double t, double& a, double& H) {
   const double H0 = p.hubble_h * kH100;
   if (p.cosmology == RH_COSMO_STATIC) {
@@ -99,6 +126,12 @@ void cosmo_at(const rh_params& p, double t, double& a, double& H) {
   } else if (p.cosmology == RH_COSMO_EDS) {
     a = std::pow(1.5 * H0 * t, 2.0 / 3.0);
     H = 2.0 / (3.0 * t);
+  } else if (p.cosmology == RH_COSMO_OPEN) {
+    const double Ok = 1.0 - p.Omega_m;
+    const double A = p.Omega_m / (2.0 * Ok), B = p.Omega_m / (2.0 * H0 * Ok * std::sqrt(Ok));
+    const double u = open_angle(t / B);
+    a = A * 2.0 * std::sinh(0.5 * u) * std::sinh(0.5 * u);
+    H = H0 * std::sqrt(p.Omega_m / (a * a * a) + Ok / (a * a));
   } else {
     const double s = std::sinh(1.5 * std::sqrt(p.Omega_L) * H0 * t);
     a = std::cbrt(p.Omega_m / p.Omega_L) * std::pow(s, 2.0 / 3.0);
@@ -159,7 +192,10 @@ bool validate(const rh_params* p, std::string& err) {
   if (!(p->hnu0_eV > 0) || !(p->sigma0_cm2 >= 0)) { err = "hnu0 > 0 and sigma0 >= 0 required"; return false; }
   if (p->rates != RH_RATES_CONST && p->rates != RH_RATES_FIT) { err = "unknown rates"; return false; }
   if (p->rates == RH_RATES_CONST && !(p->alphaB_const >= 0)) { err = "alphaB_const must be >= 0"; return false; }
-  if (p->cosmology < 0 || p->cosmology > 2) { err = "unknown cosmology"; return false; }
+  if (p->cosmology < 0 || p->cosmology > 3) { err = "unknown cosmology"; return false; }
+  if (p->cosmology == RH_COSMO_OPEN && (!(p->Omega_m > 0 && p->Omega_m < 1) || p->Omega_L != 0)) {
+    err = "open cosmology needs 0 < Omega_m < 1 and Omega_L = 0"; return false;
+  }
   if (p->cosmology != RH_COSMO_STATIC && !(p->hubble_h > 0)) { err = "hubble_h must be > 0"; return false; }
   if (p->cosmology == RH_COSMO_EDS && std::fabs(p->Omega_m - 1.0) > 1e-12) { err = "EdS needs Omega_m = 1"; return false; }
   if (p->cosmology == RH_COSMO_FLAT_LCDM &&
@@ -1258,6 +1294,12 @@ rh_status rh_cosmic_time(const rh_params* p, double a, double* t) {
   if (p->cosmology == RH_COSMO_FLAT_LCDM) {
     *t = 2.0 / (3.0 * std::sqrt(p->Omega_L) * H0) *
          std::asinh(std::sqrt(p->Omega_L / p->Omega_m) * std::pow(a, 1.5));
+    return RH_OK;
+  }
+  if (p->cosmology == RH_COSMO_OPEN) {
+    const double Ok = 1.0 - p->Omega_m;
+    const double A = p->Omega_m / (2.0 * Ok), B = p->Omega_m / (2.0 * H0 * Ok * std::sqrt(Ok));
+    *t = B * open_g(std::acosh(1.0 + a / A));
     return RH_OK;
   }
   return RH_EINVAL;

@@ -63,16 +63,19 @@ def test_compton_coefficient():
 # ---------------------------------------------------------------------------
 # cosmology: closed forms against the Friedmann equation
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("kind,h,Om,OL", [(1, 0.5, 1.0, 0.0), (2, 0.7, 0.3, 0.7)])
+@pytest.mark.parametrize("kind,h,Om,OL", [(1, 0.5, 1.0, 0.0), (2, 0.7, 0.3, 0.7),
+                                         (3, 1.0, 0.1, 0.0)])
 def test_cosmology_against_friedmann(kind, h, Om, OL):
     c = cosmology.Cosmology(kind, h, Om, OL)
     H0 = c.H0
     a_start = 1e-3
     t_start = c.time_of_a(a_start)
 
+    Ok = 1.0 - Om - OL  # curvature (open universe)
+
     def rhs(t, y):
         a = y[0]
-        return [a * H0 * math.sqrt(Om / a ** 3 + OL)]
+        return [a * H0 * math.sqrt(Om / a ** 3 + Ok / a ** 2 + OL)]
     t_end = c.time_of_z(0.0)
     ts = np.linspace(t_start, t_end, 7)
     sol = integrate.solve_ivp(rhs, (t_start, t_end), [a_start], t_eval=ts,

@@ -42,6 +42,7 @@ BC_OUTFLOW = 2
 COSMO_STATIC = 0
 COSMO_EDS = 1
 COSMO_FLAT_LCDM = 2
+COSMO_OPEN = 3
 
 # spectrum codes
 SPEC_MONO = 0
