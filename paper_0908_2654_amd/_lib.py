@@ -6,6 +6,12 @@ raises ImportError if it has not been built: there is no fallback path.
 import ctypes
 import os
 
+# PyTorch ships its own HIP runtime.  Load it before librh.so so the library
+# binds to that same runtime (one process, one runtime): loaded the other way
+# round the library gets a second runtime that does not see torch's device
+# memory or, on some boxes, any device at all.
+import torch  # noqa: F401,E402
+
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librh.so")
 

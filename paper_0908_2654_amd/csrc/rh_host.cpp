@@ -885,7 +885,13 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
                                  sizeof(double) * RS_COUNT, h->stream);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
       e5 != hipSuccess) {
-    g_last_error = "HIP initialisation failed";
+    const hipError_t es[5] = {e1, e2, e3, e4, e5};
+    const char* what[5] = {"hipGetDevice", "hipHostMalloc", "hipEventCreate", "hipEventCreate",
+                           "hipMemsetAsync (reduction counts)"};
+    int i = 0;
+    while (es[i] == hipSuccess) ++i;
+    g_last_error = std::string("HIP initialisation failed: ") + what[i] + ": " +
+                   hipGetErrorString(es[i]);
     delete h;
     return RH_EHIP;
   }

@@ -88,6 +88,14 @@ class Solver:
     def __init__(self, params: RhParams, device="cuda", stream=None):
         self.params = params
         self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a HIP device")
+        # the library records the current device at setup and launches there
+        torch.cuda.init()
+        if self.device.index is not None:
+            torch.cuda.set_device(self.device)
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.ws_bytes = workspace_bytes(params)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device) if stream is None else stream

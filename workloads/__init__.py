@@ -23,6 +23,7 @@ uniform Stromgren-sphere media follow the verification section directly.
 from __future__ import annotations
 
 import copy
+import math
 import dataclasses
 from dataclasses import dataclass, field
 from typing import Optional
@@ -180,6 +181,45 @@ CONFIGS = {
         newton_tol=1.0e-8, precision=PREC_MIXED,
         extra={"adjoint_last_steps": 8}),
 }
+
+
+# ---------------------------------------------------------------------------
+# The four cosmological Stromgren-sphere runs of the verification section
+# (its cosmology table): q0, z0, initial proper box L0, h, Omega_m, Omega_L,
+# Omega_b.  One monochromatic 13.6 eV source of 5e48 photons/s in the lower
+# corner (reflecting lower walls, outflow upper walls: the octant of a
+# sphere, so the corner cell gets Q/8), constant case-B recombination
+# (2.59e-13 cm^3/s at 1e4 K, the analytic solution's assumption), initially
+# neutral gas, E = 1e-35, from z0 to z = 0.  The comoving hydrogen density is
+# Omega_b times the critical density over m_H (at z0 = 4 this is the stated
+# initial mass density: 1.175e-28 g cm^-3 for q0 = 0.5, 2.35e-28 for 0.05).
+# ---------------------------------------------------------------------------
+SG_ROWS = [
+    (0.5, 4.0, 80.0, 0.5, 1.0, 0.0, 0.2),
+    (0.05, 4.0, 60.0, 1.0, 0.1, 0.0, 0.1),
+    (0.5, 10.0, 36.0, 0.5, 1.0, 0.0, 0.2),
+    (0.05, 10.0, 27.0, 1.0, 0.1, 0.0, 0.1),
+]
+_G_CGS = 6.674e-8
+_M_H = 1.6735575e-24
+_H100 = 3.2407789e-18  # 100 km/s/Mpc in 1/s
+
+
+def shapiro_giroux(row: int, dims=(32, 32, 32)) -> Workload:
+    """Workload of row `row` (0-3) of the verification table."""
+    q0, z0, L0_kpc, h, Om, OL, Ob = SG_ROWS[row]
+    rho_crit = 3.0 * (h * _H100) ** 2 / (8.0 * math.pi * _G_CGS)
+    return Workload(
+        name=f"shapiro_giroux_q{q0:g}_z{z0:g}", dims=tuple(dims),
+        box_comoving_cm=L0_kpc * (1.0 + z0) * KPC_CM, bc=(BC_ZEROFLUX, BC_OUTFLOW) * 3,
+        nH_mean=Ob * rho_crit / _M_H, x0=0.0, T0=1.0e4, E0=1.0e-35,
+        sources="corner", n_sources=1, Q_median=5.0e48,
+        isothermal=True, T_iso=1.0e4, spectrum=SPEC_MONO, sigma0=6.3e-18,
+        rates=RATES_CONST, alphaB_const=2.59e-13, cooling=0,
+        cosmology=COSMO_EDS if q0 == 0.5 else COSMO_OPEN, hubble_h=h, Omega_m=Om,
+        Omega_L=OL, z_start=z0, z_end=0.0, nsteps=1, theta=0.51,
+        newton_tol=1.0e-8, precision=PREC_FP64,
+        extra={"q0": q0, "z0": z0, "tau_tol": 1.0e-3})
 
 
 def get(cfg) -> Workload:
