@@ -226,10 +226,15 @@ __device__ inline D3 dsqrt(D3 a) {
   double dv = 0.5 / sv;
   return D3{sv, {a.g[0] * dv, a.g[1] * dv, a.g[2] * dv}};
 }
+__device__ inline D3 dlog(D3 a) {
+  double iv = 1.0 / a.v;
+  return D3{log(a.v), {a.g[0] * iv, a.g[1] * iv, a.g[2] * iv}};
+}
 __device__ inline D3 dmax0(D3 a) { return a.v >= 0.0 ? a : dconst(0.0); }
 __device__ inline double dexp(double a) { return exp(a); }
 __device__ inline double dpow(double a, double p) { return pow(a, p); }
 __device__ inline double dsqrt(double a) { return sqrt(a); }
+__device__ inline double dlog(double a) { return log(a); }
 __device__ inline double dmax0(double a) { return fmax(a, 0.0); }
 template <class S>
 __device__ inline S lift(double v);
@@ -239,17 +244,35 @@ template <>
 __device__ inline D3 lift<D3>(double v) { return dconst(v); }
 
 // Rate fits (Hui & Gnedin 1997 case B; Cen 1992 collisional excitation).
+// The case-B fits are powers of lambda = 315614 K / T and of 1 + (lambda /
+// c)^p; they are evaluated as exponentials of L = ln(lambda), which the
+// recombination rate and the recombination cooling share: 3 logarithms and
+// 4 exponentials instead of 6 general powers (the ALU-bound local solve
+// evaluates them in every iteration).
+constexpr double kLn315614 = 12.662275226919286;  // ln(315614)
+constexpr double kLn2p740 = 1.0079579203999789;   // ln(2.740)
+constexpr double kLn2p250 = 0.8109302162163288;   // ln(2.250)
+template <class S>
+__device__ inline S hg_ln_lambda(S T) {
+  return kLn315614 - dlog(T);
+}
+template <class S>
+__device__ inline S alpha_B_of_L(S L) {
+  S den = 1.0 + dexp(0.407 * (L - kLn2p740));
+  return 2.753e-14 * dexp(1.5 * L - 2.242 * dlog(den));
+}
+template <class S>
+__device__ inline S cool_recB_of_L(S T, S L) {
+  S den = 1.0 + dexp(0.376 * (L - kLn2p250));
+  return 3.435e-30 * T * dexp(1.970 * L - 3.720 * dlog(den));
+}
 template <class S>
 __device__ inline S alpha_B_fit(S T) {
-  S lam = 315614.0 / T;
-  S den = 1.0 + dpow(lam / 2.740, 0.407);
-  return 2.753e-14 * dpow(lam, 1.5) / dpow(den, 2.242);
+  return alpha_B_of_L(hg_ln_lambda(T));
 }
 template <class S>
 __device__ inline S cool_recB(S T) {
-  S lam = 315614.0 / T;
-  S den = 1.0 + dpow(lam / 2.250, 0.376);
-  return 3.435e-30 * T * dpow(lam, 1.970) / dpow(den, 3.720);
+  return cool_recB_of_L(T, hg_ln_lambda(T));
 }
 template <class S>
 __device__ inline S cool_collexc(S T) {
@@ -270,7 +293,9 @@ __device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, dou
     T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
   }
   S ne = (nH - n) / a3;
-  S alpha = k.rates ? alpha_B_fit(T) : lift<S>(k.alphaB);
+  const bool use_L = k.rates || (!k.iso && (k.cooling & RH_COOL_RECB));
+  const S L = use_L ? hg_ln_lambda(T) : lift<S>(0.0);
+  S alpha = k.rates ? alpha_B_of_L(L) : lift<S>(k.alphaB);
   A = alpha * ne * nH;
   B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
   if (k.iso) {
@@ -280,7 +305,7 @@ __device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, dou
   S nHI = n / a3;
   S G = (kC * k.K_G / a3) * nHI * Epos;
   S Lam = lift<S>(0.0);
-  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB(T) * ne * ne;
+  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB_of_L(T, L) * ne * ne;
   if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
   if (k.cooling & RH_COOL_COMPTON) {
     const double zp1 = 1.0 / a;
@@ -1787,6 +1812,7 @@ __device__ inline DN<NV> chain(DN<NV> a, double fv, double dfv) {
 template <int NV> __device__ inline DN<NV> dexp(DN<NV> a) { const double e = exp(a.v); return chain(a, e, e); }
 template <int NV> __device__ inline DN<NV> dpow(DN<NV> a, double p) { const double pv = pow(a.v, p); return chain(a, pv, p * pv / a.v); }
 template <int NV> __device__ inline DN<NV> dsqrt(DN<NV> a) { const double s = sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int NV> __device__ inline DN<NV> dlog(DN<NV> a) { return chain(a, log(a.v), 1.0 / a.v); }
 template <int NV> __device__ inline DN<NV> dmax0(DN<NV> a) { return a.v >= 0.0 ? a : dn_const<NV>(0.0); }
 template <int NV> __device__ inline DN<NV> dfabs(DN<NV> a) { return a.v < 0.0 ? dn_const<NV>(0.0) - a : a; }
 template <int NV> __device__ inline DN<NV> dfmax(DN<NV> a, double c) { return a.v >= c ? a : dn_const<NV>(c); }
@@ -1807,7 +1833,9 @@ __device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, doubl
     T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
   }
   S ne = (nH - n) / a3;
-  S alpha = k.rates ? alpha_B_fit(T) : lift<S>(k.alphaB);
+  const bool use_L = k.rates || (!k.iso && (k.cooling & RH_COOL_RECB));
+  const S L = use_L ? hg_ln_lambda(T) : lift<S>(0.0);
+  S alpha = k.rates ? alpha_B_of_L(L) : lift<S>(k.alphaB);
   A = alpha * ne * nH;
   B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
   if (k.iso) {
@@ -1817,7 +1845,7 @@ __device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, doubl
   S nHI = n / a3;
   S G = (kC * k.K_G / a3) * nHI * Epos;
   S Lam = lift<S>(0.0);
-  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB(T) * ne * ne;
+  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB_of_L(T, L) * ne * ne;
   if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
   if (k.cooling & RH_COOL_COMPTON) {
     const double zp1 = 1.0 / a;
