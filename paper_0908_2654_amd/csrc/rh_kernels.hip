@@ -243,6 +243,82 @@ __device__ inline double lift<double>(double v) { return v; }
 template <>
 __device__ inline D3 lift<D3>(double v) { return dconst(v); }
 
+// Forward-mode dual numbers with NV derivative slots (the local solve uses
+// two, the adjoint's local terms seven).
+template <int NV>
+struct DN {
+  double v, g[NV];
+};
+template <int NV>
+__device__ inline DN<NV> dn_const(double v) {
+  DN<NV> r;
+  r.v = v;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = 0.0;
+  return r;
+}
+template <int NV>
+__device__ inline DN<NV> dn_var(double v, int slot) {
+  DN<NV> r = dn_const<NV>(v);
+  r.g[slot] = 1.0;
+  return r;
+}
+#define RH_DN_BIN(OP, VAL, GRAD)                                                   \
+  template <int NV>                                                                \
+  __device__ inline DN<NV> operator OP(DN<NV> a, DN<NV> b) {                       \
+    DN<NV> r;                                                                      \
+    r.v = VAL;                                                                     \
+    _Pragma("unroll") for (int i = 0; i < NV; ++i) r.g[i] = GRAD;                  \
+    return r;                                                                      \
+  }
+RH_DN_BIN(+, a.v + b.v, a.g[i] + b.g[i])
+RH_DN_BIN(-, a.v - b.v, a.g[i] - b.g[i])
+RH_DN_BIN(*, a.v * b.v, a.g[i] * b.v + a.v * b.g[i])
+#undef RH_DN_BIN
+template <int NV>
+__device__ inline DN<NV> operator/(DN<NV> a, DN<NV> b) {
+  const double iv = 1.0 / b.v, q = a.v * iv;
+  DN<NV> r;
+  r.v = q;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = (a.g[i] - q * b.g[i]) * iv;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> operator+(DN<NV> a, double b) { return a + dn_const<NV>(b); }
+template <int NV> __device__ inline DN<NV> operator+(double b, DN<NV> a) { return dn_const<NV>(b) + a; }
+template <int NV> __device__ inline DN<NV> operator-(DN<NV> a, double b) { return a - dn_const<NV>(b); }
+template <int NV> __device__ inline DN<NV> operator-(double b, DN<NV> a) { return dn_const<NV>(b) - a; }
+template <int NV>
+__device__ inline DN<NV> operator*(DN<NV> a, double b) {
+  DN<NV> r;
+  r.v = a.v * b;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * b;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> operator*(double b, DN<NV> a) { return a * b; }
+template <int NV> __device__ inline DN<NV> operator/(DN<NV> a, double b) { return a * (1.0 / b); }
+template <int NV> __device__ inline DN<NV> operator/(double b, DN<NV> a) { return dn_const<NV>(b) / a; }
+template <int NV>
+__device__ inline DN<NV> chain(DN<NV> a, double fv, double dfv) {
+  DN<NV> r;
+  r.v = fv;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * dfv;
+  return r;
+}
+template <int NV> __device__ inline DN<NV> dexp(DN<NV> a) { const double e = exp(a.v); return chain(a, e, e); }
+template <int NV> __device__ inline DN<NV> dpow(DN<NV> a, double p) { const double pv = pow(a.v, p); return chain(a, pv, p * pv / a.v); }
+template <int NV> __device__ inline DN<NV> dsqrt(DN<NV> a) { const double s = sqrt(a.v); return chain(a, s, 0.5 / s); }
+template <int NV> __device__ inline DN<NV> dlog(DN<NV> a) { return chain(a, log(a.v), 1.0 / a.v); }
+template <int NV> __device__ inline DN<NV> dmax0(DN<NV> a) { return a.v >= 0.0 ? a : dn_const<NV>(0.0); }
+template <int NV> __device__ inline DN<NV> dfabs(DN<NV> a) { return a.v < 0.0 ? dn_const<NV>(0.0) - a : a; }
+template <int NV> __device__ inline DN<NV> dfmax(DN<NV> a, double c) { return a.v >= c ? a : dn_const<NV>(c); }
+template <>
+__device__ inline DN<7> lift<DN<7>>(double v) { return dn_const<7>(v); }
+template <>
+__device__ inline DN<2> lift<DN<2>>(double v) { return dn_const<2>(v); }
+
 // Rate fits (Hui & Gnedin 1997 case B; Cen 1992 collisional excitation).
 // The case-B fits are powers of lambda = 315614 K / T and of 1 + (lambda /
 // c)^p; they are evaluated as exponentials of L = ln(lambda), which the
@@ -279,6 +355,47 @@ __device__ inline S cool_collexc(S T) {
   return 7.5e-19 * dexp(-118348.0 / T) / (1.0 + dsqrt(T / 1.0e5));
 }
 
+// The temperature fits are functions of T alone: evaluate them once with one
+// derivative slot (d/dT) and chain the result into the caller's dual numbers.
+__device__ inline double dval(double a) { return a; }
+__device__ inline double dval(const D3& a) { return a.v; }
+template <int NV>
+__device__ inline double dval(const DN<NV>& a) { return a.v; }
+__device__ inline double dchain(double, double fv, double) { return fv; }
+__device__ inline D3 dchain(const D3& x, double fv, double dfv) {
+  return D3{fv, {x.g[0] * dfv, x.g[1] * dfv, x.g[2] * dfv}};
+}
+template <int NV>
+__device__ inline DN<NV> dchain(const DN<NV>& x, double fv, double dfv) {
+  return chain(x, fv, dfv);
+}
+struct TFits {
+  double alpha, dalpha, recB, drecB, ce, dce;  // values and d/dT
+};
+__device__ inline TFits t_fits(double T, bool alpha, bool recB, bool ce) {
+  TFits f{};
+  const DN<1> Td = dn_var<1>(T, 0);
+  if (alpha || recB) {
+    const DN<1> L = hg_ln_lambda(Td);
+    if (alpha) {
+      const DN<1> a = alpha_B_of_L(L);
+      f.alpha = a.v;
+      f.dalpha = a.g[0];
+    }
+    if (recB) {
+      const DN<1> r = cool_recB_of_L(Td, L);
+      f.recB = r.v;
+      f.drecB = r.g[0];
+    }
+  }
+  if (ce) {
+    const DN<1> c = cool_collexc(Td);
+    f.ce = c.v;
+    f.dce = c.g[0];
+  }
+  return f;
+}
+
 // Rates of the local ODEs at a state: dn/dt = A - B n, de/dt = q - 2 H e.
 template <class S>
 __device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, double a, S& A,
@@ -293,9 +410,10 @@ __device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, dou
     T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
   }
   S ne = (nH - n) / a3;
-  const bool use_L = k.rates || (!k.iso && (k.cooling & RH_COOL_RECB));
-  const S L = use_L ? hg_ln_lambda(T) : lift<S>(0.0);
-  S alpha = k.rates ? alpha_B_of_L(L) : lift<S>(k.alphaB);
+  const bool fit_recB = !k.iso && (k.cooling & RH_COOL_RECB);
+  const bool fit_ce = !k.iso && (k.cooling & RH_COOL_COLLEXC);
+  const TFits tf = t_fits(dval(T), k.rates, fit_recB, fit_ce);
+  S alpha = k.rates ? dchain(T, tf.alpha, tf.dalpha) : lift<S>(k.alphaB);
   A = alpha * ne * nH;
   B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
   if (k.iso) {
@@ -305,8 +423,8 @@ __device__ inline void local_rates(const StepK& k, S E, S e, S n, double nH, dou
   S nHI = n / a3;
   S G = (kC * k.K_G / a3) * nHI * Epos;
   S Lam = lift<S>(0.0);
-  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB_of_L(T, L) * ne * ne;
-  if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
+  if (fit_recB) Lam = Lam + dchain(T, tf.recB, tf.drecB) * ne * ne;
+  if (fit_ce) Lam = Lam + dchain(T, tf.ce, tf.dce) * ne * nHI;
   if (k.cooling & RH_COOL_COMPTON) {
     const double zp1 = 1.0 / a;
     Lam = Lam + (k.compton * zp1 * zp1 * zp1 * zp1) * (T - kTcmb0 * zp1) * ne;
@@ -332,7 +450,8 @@ __device__ inline void local_S(const StepK& k, S E, S e, S n, double nH, double 
 // ---------------------------------------------------------------------------
 // K1: local solve / evaluation
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
+// at least 3 waves per SIMD (<= 168 VGPRs): the FP64 chemistry is latency-bound at 2
+__global__ void __launch_bounds__(kBlock, 3)
 k_local(StepK k, LocalArgs a, double* __restrict__ part) {
   double sfn = 0.0, sfe = 0.0, fail = 0.0, itmax = 0.0, bad = 0.0;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
@@ -367,9 +486,10 @@ k_local(StepK k, LocalArgs a, double* __restrict__ part) {
       if (!k.iso) e = fmax(e, 1e-300);
       bool conv = false;
       for (its = 1; its <= 80; ++its) {
-        D3 Sn, Se;
-        D3 nd = dvar(n, 0), ed = dvar(e, 1), Ed = dconst(E);
-        local_S<D3>(k, Ed, ed, nd, nH, nn, en, Rn, qn, Sn, Se);
+        // E is fixed here: two derivative slots (n, e)
+        DN<2> Sn, Se;
+        local_S<DN<2>>(k, dn_const<2>(E), dn_var<2>(e, 1), dn_var<2>(n, 0), nH, nn, en, Rn, qn,
+                       Sn, Se);
         const double fn = n - Sn.v;
         const double b11 = 1.0 - Sn.g[0];
         double dn, de = 0.0;
@@ -442,7 +562,11 @@ k_local(StepK k, LocalArgs a, double* __restrict__ part) {
 }
 
 void launch_local(hipStream_t s, const StepK& k, const LocalArgs& a, double* part) {
-  hipLaunchKernelGGL(k_local, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, a, part);
+  // many small workgroups: the ALU-bound solve runs at 3 waves per SIMD, which
+  // the fixed reduction grid would fill only in one and a third rounds
+  const long long g = (k.N + kBlock - 1) / kBlock;
+  const int grid = (int)(g < kPartCap ? g : kPartCap);
+  hipLaunchKernelGGL(k_local, dim3(grid), dim3(kBlock), 0, s, k, a, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,79 +1870,6 @@ void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT
 // ---------------------------------------------------------------------------
 // adjoint of the step (implicit-function theorem at the converged U^{n+1})
 // ---------------------------------------------------------------------------
-// Forward-mode dual numbers with NV derivative slots.
-template <int NV>
-struct DN {
-  double v, g[NV];
-};
-template <int NV>
-__device__ inline DN<NV> dn_const(double v) {
-  DN<NV> r;
-  r.v = v;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = 0.0;
-  return r;
-}
-template <int NV>
-__device__ inline DN<NV> dn_var(double v, int slot) {
-  DN<NV> r = dn_const<NV>(v);
-  r.g[slot] = 1.0;
-  return r;
-}
-#define RH_DN_BIN(OP, VAL, GRAD)                                                   \
-  template <int NV>                                                                \
-  __device__ inline DN<NV> operator OP(DN<NV> a, DN<NV> b) {                       \
-    DN<NV> r;                                                                      \
-    r.v = VAL;                                                                     \
-    _Pragma("unroll") for (int i = 0; i < NV; ++i) r.g[i] = GRAD;                  \
-    return r;                                                                      \
-  }
-RH_DN_BIN(+, a.v + b.v, a.g[i] + b.g[i])
-RH_DN_BIN(-, a.v - b.v, a.g[i] - b.g[i])
-RH_DN_BIN(*, a.v * b.v, a.g[i] * b.v + a.v * b.g[i])
-#undef RH_DN_BIN
-template <int NV>
-__device__ inline DN<NV> operator/(DN<NV> a, DN<NV> b) {
-  const double iv = 1.0 / b.v, q = a.v * iv;
-  DN<NV> r;
-  r.v = q;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = (a.g[i] - q * b.g[i]) * iv;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> operator+(DN<NV> a, double b) { return a + dn_const<NV>(b); }
-template <int NV> __device__ inline DN<NV> operator+(double b, DN<NV> a) { return dn_const<NV>(b) + a; }
-template <int NV> __device__ inline DN<NV> operator-(DN<NV> a, double b) { return a - dn_const<NV>(b); }
-template <int NV> __device__ inline DN<NV> operator-(double b, DN<NV> a) { return dn_const<NV>(b) - a; }
-template <int NV>
-__device__ inline DN<NV> operator*(DN<NV> a, double b) {
-  DN<NV> r;
-  r.v = a.v * b;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * b;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> operator*(double b, DN<NV> a) { return a * b; }
-template <int NV> __device__ inline DN<NV> operator/(DN<NV> a, double b) { return a * (1.0 / b); }
-template <int NV> __device__ inline DN<NV> operator/(double b, DN<NV> a) { return dn_const<NV>(b) / a; }
-template <int NV>
-__device__ inline DN<NV> chain(DN<NV> a, double fv, double dfv) {
-  DN<NV> r;
-  r.v = fv;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * dfv;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> dexp(DN<NV> a) { const double e = exp(a.v); return chain(a, e, e); }
-template <int NV> __device__ inline DN<NV> dpow(DN<NV> a, double p) { const double pv = pow(a.v, p); return chain(a, pv, p * pv / a.v); }
-template <int NV> __device__ inline DN<NV> dsqrt(DN<NV> a) { const double s = sqrt(a.v); return chain(a, s, 0.5 / s); }
-template <int NV> __device__ inline DN<NV> dlog(DN<NV> a) { return chain(a, log(a.v), 1.0 / a.v); }
-template <int NV> __device__ inline DN<NV> dmax0(DN<NV> a) { return a.v >= 0.0 ? a : dn_const<NV>(0.0); }
-template <int NV> __device__ inline DN<NV> dfabs(DN<NV> a) { return a.v < 0.0 ? dn_const<NV>(0.0) - a : a; }
-template <int NV> __device__ inline DN<NV> dfmax(DN<NV> a, double c) { return a.v >= c ? a : dn_const<NV>(c); }
-template <>
-__device__ inline DN<7> lift<DN<7>>(double v) { return dn_const<7>(v); }
-
 // Local rates with the hydrogen density as an independent variable.
 template <class S>
 __device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, double a, S& A, S& B,
@@ -1833,9 +1884,10 @@ __device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, doubl
     T = ((k.gamma - 1.0) * kMH / kKB) * mu * e;
   }
   S ne = (nH - n) / a3;
-  const bool use_L = k.rates || (!k.iso && (k.cooling & RH_COOL_RECB));
-  const S L = use_L ? hg_ln_lambda(T) : lift<S>(0.0);
-  S alpha = k.rates ? alpha_B_of_L(L) : lift<S>(k.alphaB);
+  const bool fit_recB = !k.iso && (k.cooling & RH_COOL_RECB);
+  const bool fit_ce = !k.iso && (k.cooling & RH_COOL_COLLEXC);
+  const TFits tf = t_fits(dval(T), k.rates, fit_recB, fit_ce);
+  S alpha = k.rates ? dchain(T, tf.alpha, tf.dalpha) : lift<S>(k.alphaB);
   A = alpha * ne * nH;
   B = alpha * ne + (kC * k.K_Gamma / a3) * Epos;
   if (k.iso) {
@@ -1845,8 +1897,8 @@ __device__ inline void local_rates_nh(const StepK& k, S E, S e, S n, S nH, doubl
   S nHI = n / a3;
   S G = (kC * k.K_G / a3) * nHI * Epos;
   S Lam = lift<S>(0.0);
-  if (k.cooling & RH_COOL_RECB) Lam = Lam + cool_recB_of_L(T, L) * ne * ne;
-  if (k.cooling & RH_COOL_COLLEXC) Lam = Lam + cool_collexc(T) * ne * nHI;
+  if (fit_recB) Lam = Lam + dchain(T, tf.recB, tf.drecB) * ne * ne;
+  if (fit_ce) Lam = Lam + dchain(T, tf.ce, tf.dce) * ne * nHI;
   if (k.cooling & RH_COOL_COMPTON) {
     const double zp1 = 1.0 / a;
     Lam = Lam + (k.compton * zp1 * zp1 * zp1 * zp1) * (T - kTcmb0 * zp1) * ne;
