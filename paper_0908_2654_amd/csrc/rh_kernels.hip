@@ -1484,8 +1484,69 @@ __global__ void __launch_bounds__(kBlock) k_prolong(LevelK<T> c, LevelK<T> f) {
   }
 }
 
+// The same prolongation with one thread per coarse cell: its 8 fine children
+// need only the 3x3x3 coarse neighbourhood (27 loads for 8 outputs instead of
+// 8 per output), and children adjacent in z are read and written as pairs.
+// Per child the sum is k_prolong's, in its order.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_prolong_cc(LevelK<T> c, LevelK<T> f) {
+  const int cplane = c.ny * c.nz, fplane = f.ny * f.nz;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < (int)c.N;
+       idx += blockDim.x * gridDim.x) {
+    const int I = idx / cplane, rem = idx - I * cplane;
+    const int J = rem / c.nz, K = rem - J * c.nz;
+    // coarse indices below / at / above along each axis, with k_prolong's
+    // boundary rule (mirror: the cell itself; periodic: wrap)
+    auto nb = [](int v, int n, int per, int s) {
+      const int u = v + s;
+      if (u >= 0 && u < n) return u;
+      return per ? (u + n) % n : v;
+    };
+    const int Ic[3] = {nb(I, c.nx, c.per[0], -1), I, nb(I, c.nx, c.per[0], 1)};
+    const int Jc[3] = {nb(J, c.ny, c.per[1], -1), J, nb(J, c.ny, c.per[1], 1)};
+    const int Kc[3] = {nb(K, c.nz, c.per[2], -1), K, nb(K, c.nz, c.per[2], 1)};
+    double cv[3][3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cv[a][b][d] = (double)c.x[Ic[a] * cplane + Jc[b] * c.nz + Kc[d]];
+    const double w[2] = {0.75, 0.25};
+#pragma unroll
+    for (int ca = 0; ca < 2; ++ca)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        // child (2I+ca, 2J+cb, 2K+cd): own coarse index, then the one on its side
+        const int ia[2] = {1, ca ? 2 : 0}, jb[2] = {1, cb ? 2 : 0};
+        const int fi = (2 * I + ca) * fplane + (2 * J + cb) * f.nz + 2 * K;
+        T out[2];
+#pragma unroll
+        for (int cd = 0; cd < 2; ++cd) {
+          const int kd[2] = {1, cd ? 2 : 0};
+          double s = 0.0;
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+              for (int d = 0; d < 2; ++d) s += w[a] * w[b] * w[d] * cv[ia[a]][jb[b]][kd[d]];
+          out[cd] = (T)((double)f.x[fi + cd] + s);
+        }
+        f.x[fi] = out[0];
+        f.x[fi + 1] = out[1];
+      }
+  }
+}
+
 template <class T>
 void launch_prolong(hipStream_t s, const LevelK<T>& c, const LevelK<T>& f) {
+  if (c.N < (1LL << 31) / 8 && f.nx == 2 * c.nx && f.ny == 2 * c.ny && f.nz == 2 * c.nz) {
+    const long long g = (c.N + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_prolong_cc<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock),
+                       0, s, c, f);
+    return;
+  }
   long long g = (f.N + kBlock - 1) / kBlock;
   hipLaunchKernelGGL((k_prolong<T>), dim3((unsigned)(g < 65536 ? g : 65536)), dim3(kBlock), 0, s,
                      c, f);
