@@ -715,12 +715,19 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
   double* p_in = h->pa;
   double* p_out = h->pb;
   const double* const cf[3] = {h->cf64[0], h->cf64[1], h->cf64[2]};
+  // x += alpha_j p_j of an update is applied by the next direction kernel
+  // (which reads p_j anyway) or, after the last update, by one axpy
+  double alpha_prev = 0.0;
+  bool pending = false;
+  const double* p_last = nullptr;
   for (int j = 1; j <= max_it; ++j) {
     {
       Timed tm(h, KK_PCG_DIR);
       // z = sigma_b * (V-cycle output): sigma_b is still the scale of that V-cycle's input
+      const XFold xf{x, alpha_prev, pending ? (j == 2 ? 1 : 2) : 0};
       launch_pcg_dir<T>(h->stream, k, h->diag64, cf, L[0].x, sigma_b, p_in, p_out, h->q64, beta,
-                        j == 1, h->part);
+                        j == 1, xf, h->part);
+      pending = false;
     }
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, slot_bit(RS_PQ))) != RH_OK) return st;
@@ -732,9 +739,12 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     const double alpha = rz / pq;
     {
       Timed tm(h, KK_PCG_UPD);
-      launch_pcg_update<T>(h->stream, k, alpha, p_out, h->q64, x, h->r64, 1.0 / rmax_cur, L[0].b,
-                           j == 1, h->part);
+      launch_pcg_update<T>(h->stream, k, alpha, p_out, h->q64, nullptr, h->r64, 1.0 / rmax_cur,
+                           L[0].b, j == 1, h->part);
     }
+    alpha_prev = alpha;
+    pending = true;
+    p_last = p_out;
     HIPCHK(hipGetLastError());
     sigma_b = rmax_cur;
     if ((st = sync_reductions(h, slot_bit(RS_FE2) | slot_bit(RS_R2) | slot_bit(RS_RMAX))) != RH_OK) return st;
@@ -756,6 +766,11 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     beta = -alpha * h->hred[RS_ZQ] / rz;
     rz = rz_new;
     std::swap(p_in, p_out);
+  }
+  if (pending) {
+    Timed tm(h, KK_PCG_UPD);
+    launch_xaxpy(h->stream, h->N, alpha_prev, p_last, x, *its_out == 1);
+    HIPCHK(hipGetLastError());
   }
   *w_out = w;
   *l2_out = l2;

@@ -177,10 +177,20 @@ void launch_accum_defect(hipStream_t s, const StepK& k, const DefectArgs& a, con
 
 // p_out = z + beta p_in (z = sigma zT; p_out = z when first), q = S p_out and
 // the partial sums of p_out . q
+// The previous iteration's x update folded into the direction kernel:
+// mode 0 none, 1 x = alpha p_in, 2 x += alpha p_in (p_in is that iteration's p).
+struct XFold {
+  double* x;
+  double alpha;
+  int mode;
+};
 template <class T>
 void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
                     const T* zT, double sigma, const double* p_in, double* p_out, double* q,
-                    double beta, int first, double* part);
+                    double beta, int first, const XFold& xf, double* part);
+// x = (first ? 0 : x) + alpha p
+void launch_xaxpy(hipStream_t s, long long N, double alpha, const double* p, double* x, int first);
+// r -= alpha q, b = r * inv_sigma, norms of r; x += alpha p unless x == NULL
 template <class T>
 void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double* p,
                        const double* q, double* x, double* r, double inv_sigma, T* b, int first,

@@ -1630,7 +1630,7 @@ k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ c
           const double* __restrict__ cfy, const double* __restrict__ cfz,
           const T* __restrict__ zT, double sigma, const double* __restrict__ p_in,
           double* __restrict__ p_out, double* __restrict__ q, double beta, int first,
-          double* __restrict__ part) {
+          double* __restrict__ xv, double alpha_prev, int xmode, double* __restrict__ part) {
   const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
                       k.bc[4] == RH_BC_PERIODIC};
   const int nd[3] = {k.nx, k.ny, k.nz};
@@ -1661,6 +1661,7 @@ k_pcg_dir(StepK k, const double* __restrict__ diag, const double* __restrict__ c
     p_out[idx] = pP;
     q[idx] = qP;
     pq += pP * qP;
+    if (xmode) xv[idx] = (xmode == 2 ? xv[idx] : 0.0) + alpha_prev * p_in[idx];
   }
   double v[1] = {pq};
   const int im[1] = {0};
@@ -1684,6 +1685,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
                 const double* __restrict__ cfy, const double* __restrict__ cfz,
                 const T* __restrict__ zT, double sigma, const double* __restrict__ p_in,
                 double* __restrict__ p_out, double* __restrict__ q, double beta, int first, int xc,
+                double* __restrict__ xv, double alpha_prev, int xmode,
                 double* __restrict__ part) {
   constexpr int TY = kDirTY, TZ = kDirTZ, HZ = TZ + 2, PL = (TY + 2) * HZ;
   constexpr int NR = TY / (kBlock / 64);  // own rows per thread
@@ -1769,6 +1771,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
   };
   double pm[NR], pc[NR], pn[NR], c0m[NR];
   double zo[NR], po[NR];  // own raw at x+2 (in flight)
+  double pin_c[NR], pin_n[NR], xcur[NR], xnext[NR];  // p_in at x, x+1; x at x, x+1
   double rz1, rp1, rz2, rp2;  // ring raw at x+1 (ready) and x+2 (in flight)
   Coef C, Cn;
   // prologue: planes xa-1, xa, xa+1 of p; plane xa in LDS; coefficients of xa
@@ -1781,8 +1784,12 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
       pm[m] = form(a, b);
       raw(xa, own[m], a, b);
       pc[m] = form(a, b);
+      pin_c[m] = b;
       raw(xa + 1, own[m], a, b);
       pn[m] = form(a, b);
+      pin_n[m] = b;
+      xcur[m] = (xmode == 2 && real[m]) ? xv[xa * plane + own[m]] : 0.0;
+      xnext[m] = 0.0;
       pl[xa & 1][li[m]] = pc[m];
       c0m[m] = (gxm >= 0 && own[m] >= 0) ? cfx[gxm * plane + own[m]] : 0.0;
     }
@@ -1804,6 +1811,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
       zo[m] = 0.0;
       po[m] = 0.0;
       if (x + 2 <= xb) raw(x + 2, own[m], zo[m], po[m]);
+      if (xmode == 2 && real[m] && x + 1 < xb) xnext[m] = xv[(x + 1) * plane + own[m]];
     }
     rz2 = rp2 = 0.0;
     if (r_li >= 0 && x + 2 < xb) raw(x + 2, r_off, rz2, rp2);
@@ -1825,6 +1833,8 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
       p_out[P] = pc[m];
       q[P] = qv;
       acc += pc[m] * qv;
+      // the previous iteration's x += alpha p (p_in is that p)
+      if (xmode) xv[P] = (xmode == 2 ? xcur[m] : 0.0) + alpha_prev * pin_c[m];
     }
     // plane x+1 into the other LDS buffer (its readers finished before the
     // last barrier)
@@ -1841,6 +1851,9 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
       pm[m] = pc[m];
       pc[m] = pn[m];
       pn[m] = form(zo[m], po[m]);
+      pin_c[m] = pin_n[m];
+      pin_n[m] = po[m];
+      xcur[m] = xnext[m];
     }
     rz1 = rz2;
     rp1 = rp2;
@@ -1855,7 +1868,7 @@ k_pcg_dir_march(StepK k, const double* __restrict__ diag, const double* __restri
 template <class T>
 void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const double* const cf[3],
                     const T* zT, double sigma, const double* p_in, double* p_out, double* q,
-                    double beta, int first, double* part) {
+                    double beta, int first, const XFold& xf, double* part) {
   const int nty = (k.ny + kDirTY - 1) / kDirTY, ntz = (k.nz + kDirTZ - 1) / kDirTZ;
   const long long tiles = (long long)nty * ntz;
   if (k.nz >= kDirTZ && k.ny >= kDirTY && k.nx >= 2 && k.N < (1LL << 31) && tiles <= kPartCap) {
@@ -1864,11 +1877,13 @@ void launch_pcg_dir(hipStream_t s, const StepK& k, const double* diag, const dou
     const int xc = (k.nx + ncx - 1) / ncx;
     ncx = (k.nx + xc - 1) / xc;
     hipLaunchKernelGGL((k_pcg_dir_march<T>), dim3((unsigned)(tiles * ncx)), dim3(kBlock), 0, s, k,
-                       diag, cf[0], cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, xc, part);
+                       diag, cf[0], cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, xc,
+                       xf.x, xf.alpha, xf.mode, part);
     return;
   }
   hipLaunchKernelGGL((k_pcg_dir<T>), dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, diag, cf[0],
-                     cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, part);
+                     cf[1], cf[2], zT, sigma, p_in, p_out, q, beta, first, xf.x, xf.alpha,
+                     xf.mode, part);
 }
 
 // B: x += alpha p;  r -= alpha q;  norms of r;  b = r * inv_sigma (preconditioner input)
@@ -1880,7 +1895,8 @@ k_pcg_update(StepK k, double alpha, const double* __restrict__ p, const double* 
   double s2w = 0.0, s2 = 0.0, rmax = 0.0;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
        idx += (long long)blockDim.x * gridDim.x) {
-    x[idx] = (first ? 0.0 : x[idx]) + alpha * p[idx];
+    // x == NULL: x += alpha p is left to the next direction kernel
+    if (x) x[idx] = (first ? 0.0 : x[idx]) + alpha * p[idx];
     const double rv = r[idx] - alpha * q[idx];
     r[idx] = rv;
     b[idx] = (T)(rv * inv_sigma);
@@ -1892,6 +1908,19 @@ k_pcg_update(StepK k, double alpha, const double* __restrict__ p, const double* 
   const int im[3] = {0, 1, 0};
   const int sl[3] = {RS_FE2, RS_RMAX, RS_R2};
   block_reduce_store<3>(v, im, sl, part);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_xaxpy(long long N, double alpha, const double* __restrict__ p, double* __restrict__ x,
+        int first) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+       idx += (long long)blockDim.x * gridDim.x)
+    x[idx] = (first ? 0.0 : x[idx]) + alpha * p[idx];
+}
+
+void launch_xaxpy(hipStream_t s, long long N, double alpha, const double* p, double* x,
+                  int first) {
+  hipLaunchKernelGGL(k_xaxpy, dim3(red_grid(N)), dim3(kBlock), 0, s, N, alpha, p, x, first);
 }
 
 template <class T>
@@ -2150,7 +2179,7 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
                                       const double*, const double*, double*);                 \
   template void launch_pcg_dir<T>(hipStream_t, const StepK&, const double*,                   \
                                   const double* const[3], const T*, double, const double*,    \
-                                  double*, double*, double, int, double*);
+                                  double*, double*, double, int, const XFold&, double*);
 RH_INST(float)
 RH_INST(double)
 template void launch_coarsen_faces<double, double>(hipStream_t, int, int, int,
