@@ -35,6 +35,8 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
         # one colour of a sweep: other-colour x, own b and diag, all three
         # + face arrays (own + faces and the neighbours' - faces), own x written
         "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
+        # the V-cycle's last sweep, which also reads r and q for z.r, z.q
+        "rbgs_fine_dots": 7 * T + 2 * 8,
         # residual fused with the restriction (x, b, diag, 3 faces in; coarse
         # right-hand side out), as the benchmark sizes run it
         "mg_residual_fine": 6 * T + T / 8,

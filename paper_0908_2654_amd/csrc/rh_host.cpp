@@ -244,7 +244,8 @@ struct StateBuf {
 
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
-  KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_COUNT
+  KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_RBGS0D,
+  KK_COUNT
 };
 
 struct rh_handle {
@@ -284,6 +285,9 @@ struct rh_handle {
   // statistics of the current call
   int lin_its, local_its_max;
   double last_E_s = 1.0;  // E_s of the last step set up (weight of E in the norms)
+  // conjugate-gradient dot products requested from the V-cycle's last sweep
+  SweepDots dots{};
+  bool dots_wanted = false, dots_done = false;
   double lin_res_max;
 };
 
@@ -564,15 +568,24 @@ rh_status coarse_setup(rh_handle* h) {
 
 // One red-black sweep on level l: fused (x -> x2, then swap) when the level
 // fits the marching tiles, else colour by colour in place.
+// last: the last sweep of the V-cycle on this level; on the finest level it
+// takes over the conjugate-gradient dot products when the caller asked for
+// them (h->dots) and the sweep is fused
 template <class T>
-void sweep(rh_handle* h, int l, int first_color, int zero_init) {
+void sweep(rh_handle* h, int l, int first_color, int zero_init, bool last = false) {
   LevelK<T>* L = levels<T>(h);
   // auto: the fused sweep only where it gets enough workgroups to fill the chip
   const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
   if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
-    {
+    const bool dots = l == 0 && last && h->dots_wanted;
+    if (dots) {
+      Timed tm(h, KK_RBGS0D);
+      h->dots_done = launch_rbgs_march<T>(h->stream, L[l], first_color, zero_init, 1, min_tiles,
+                                          &h->dots);
+    }
+    if (!h->dots_done || !dots) {
       Timed tm(h, l == 0 ? KK_RBGS0 : KK_COARSE);
-      launch_rbgs_march<T>(h->stream, L[l], first_color, zero_init, l == 0, min_tiles);
+      launch_rbgs_march<T>(h->stream, L[l], first_color, zero_init, l == 0, min_tiles, nullptr);
     }
     std::swap(L[l].x, L[l].x2);
     return;
@@ -611,7 +624,7 @@ void vcycle(rh_handle* h, int l) {
   residual_restrict<T>(h, l);
   vcycle<T>(h, l + 1);
   { Timed tm(h, l == 0 ? KK_PROLONG0 : KK_COARSE); launch_prolong<T>(s, L[l + 1], L[l]); }
-  for (int it = 0; it < h->p.mg_post; ++it) sweep<T>(h, l, 1, 0);
+  for (int it = 0; it < h->p.mg_post; ++it) sweep<T>(h, l, 1, 0, it == h->p.mg_post - 1);
 }
 
 // Defect correction: S dE = rS with V-cycles in T and FP64 residuals.
@@ -681,6 +694,22 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
 // Flexible preconditioned conjugate gradients on S x = rS in FP64 with one
 // V-cycle in T as the preconditioner (the symmetric V-cycle makes plain CG
 // valid in exact arithmetic; the flexible beta absorbs FP32 rounding).
+// One V-cycle as the preconditioner (z_T = V(b)).  The partial sums of z.r
+// and z.q (z = sigma z_T; q may be NULL) come from the V-cycle's last sweep
+// on the finest level when that sweep is fused, else from a pass of their own.
+template <class T>
+void precondition(rh_handle* h, const StepK& k, double sigma, const double* q) {
+  h->dots = SweepDots{sigma, h->r64, q, h->part};
+  h->dots_wanted = true;
+  h->dots_done = false;
+  vcycle<T>(h, 0);
+  h->dots_wanted = false;
+  if (!h->dots_done) {
+    Timed tm(h, KK_PCG_PRE);
+    launch_pcg_precond<T>(h->stream, k, sigma, levels<T>(h)[0].x, h->r64, q, h->part);
+  }
+}
+
 template <class T>
 rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w, double target_2,
                     int max_it, double** x_final, int* its_out, double* w_out, double* l2_out) {
@@ -702,11 +731,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     Timed tm(h, KK_CAST);
     launch_cast_scale<T>(h->stream, h->N, h->r64, 1.0 / sigma_b, L[0].b);
   }
-  vcycle<T>(h, 0);
-  {
-    Timed tm(h, KK_PCG_PRE);
-    launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, nullptr, h->part);
-  }
+  precondition<T>(h, k, sigma_b, nullptr);
   HIPCHK(hipGetLastError());
   if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;
   double rz = h->hred[RS_ZR];
@@ -755,11 +780,7 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     if (!std::isfinite(w) || !std::isfinite(l2))
       return fail(h, RH_ELINEAR, "non-finite linear residual");
     if (w <= target_w || l2 <= target_2 || rmax_cur == 0.0) break;
-    vcycle<T>(h, 0);
-    {
-      Timed tm(h, KK_PCG_PRE);
-      launch_pcg_precond<T>(h->stream, k, sigma_b, L[0].x, h->r64, h->q64, h->part);
-    }
+    precondition<T>(h, k, sigma_b, h->q64);
     HIPCHK(hipGetLastError());
     if ((st = sync_reductions(h, slot_bit(RS_ZR) | slot_bit(RS_ZQ))) != RH_OK) return st;
     const double rz_new = h->hred[RS_ZR];

@@ -140,9 +140,19 @@ void launch_rbgs(hipStream_t s, const LevelK<T>& l, int color, int zero_init, in
 // One full red-black sweep (first_color, then the other) reading l.x and
 // writing l.x2; returns false (nothing launched) unless rbgs_march_fits(l,
 // min_tiles), and the caller then sweeps colour by colour in place.
+// With dots != NULL (finest level, last sweep of a V-cycle) the launch also
+// stores the block partials of z.r (RS_ZR) and z.q (RS_ZQ, q may be NULL)
+// for z = sigma * (the sweep's output); it then returns false, launching
+// nothing, if the grid has more workgroups than the partial buffer holds.
+struct SweepDots {
+  double sigma;
+  const double* r;
+  const double* q;
+  double* part;
+};
 template <class T>
 bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
-                       int fine, long long min_tiles);
+                       int fine, long long min_tiles, const SweepDots* dots);
 // The level has a second buffer, the shape the marching tiles need, fewer
 // than 2^31 cells and at least min_tiles tiles (one workgroup each).
 template <class T>

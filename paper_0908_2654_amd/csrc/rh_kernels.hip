@@ -36,10 +36,10 @@ __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
-template <int NV>
+template <int NV, int NTH = kBlock>
 __device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max)[NV],
                                           const int (&slot)[NV], double* part) {
-  __shared__ double sh[NV][kBlock / 64];
+  __shared__ double sh[NV][NTH / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -51,7 +51,7 @@ __device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       double v = sh[q][0];
-      for (int w = 1; w < kBlock / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
+      for (int w = 1; w < NTH / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
       part[(long long)slot[q] * kPartCap + blockIdx.x] = v;
       if (blockIdx.x == 0) part[(long long)RS_COUNT * kPartCap + slot[q]] = (double)gridDim.x;
     }
@@ -949,9 +949,16 @@ __device__ inline int xcd_tile(int bid, int nb) {
   return xcd * q + min(xcd, r) + k;
 }
 
-template <class T, int TY, int TZ, int NT, int FINE>
+//
+// DOTS: the sweep's output is the preconditioned residual z_T of the
+// conjugate-gradient iteration (last sweep of a V-cycle on the finest
+// level); the block partials of z.r and z.q with z = sigma z_T are formed
+// while writing it (q may be null), in place of a separate pass.
+template <class T, int TY, int TZ, int NT, int FINE, int DOTS>
 __global__ void __launch_bounds__(NT)
-k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
+k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
+             const double* __restrict__ rv, const double* __restrict__ qv,
+             double* __restrict__ part) {
   static_assert(TZ % 2 == 0, "z-pairs need an even tile width");
   constexpr int HY = TY + 4, HZ = TZ + 4, PL = HY * HZ;   // x planes (halo 2)
   constexpr int CR = TY + 3, CZ = TZ + 3, CN = CR * CZ;    // staged coefficient region
@@ -1083,6 +1090,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
     for (int j = 0; j < NP; ++j)
       if (qs[j] >= 0) cur[qs[j]] = nv[j];
   };
+  double zr = 0.0, zq = 0.0;
   Buf A, B;
   fetch_x(xa - 2, A);
   stash_x(xa - 2, A);
@@ -1114,7 +1122,16 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
       for (int t = tid; t < TY * TZ; t += NT) {
         const int lz = t % TZ, ly = t / TZ;
         const int gy = ty * TY + ly, gz = tz * TZ + lz;
-        if (gy < l.ny && gz < l.nz) l.x2[q * plane + gy * l.nz + gz] = src[(ly + 2) * HZ + lz + 2];
+        if (gy < l.ny && gz < l.nz) {
+          const int P = q * plane + gy * l.nz + gz;
+          const T v = src[(ly + 2) * HZ + lz + 2];
+          l.x2[P] = v;
+          if (DOTS) {
+            const double zv = sigma * (double)v;
+            zr += zv * rv[P];
+            if (qv) zq += zv * qv[P];
+          }
+        }
       }
     }
     // the slots of plane p-2 (x) and p-1 (coefficients) are free once plane
@@ -1126,6 +1143,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc) {
   for (int p = xa - 1; p <= xb; p += 2) {
     step(p, A, B);
     if (p + 1 <= xb) step(p + 1, B, A);
+  }
+  if (DOTS) {
+    double v[2] = {zr, zq};
+    const int im[2] = {0, 0};
+    const int sl[2] = {RS_ZR, RS_ZQ};
+    block_reduce_store<2, NT>(v, im, sl, part);
   }
 }
 
@@ -1153,18 +1176,22 @@ bool rbgs_march_fits(const LevelK<T>& l, long long min_tiles) {
 
 template <class T>
 bool launch_rbgs_march(hipStream_t s, const LevelK<T>& l, int first_color, int zero_init,
-                       int fine, long long min_tiles) {
+                       int fine, long long min_tiles, const SweepDots* dots) {
   constexpr int TY = MarchTile<T>::TY, TZ = MarchTile<T>::TZ;
   const int xc = march_chunk(l, min_tiles);
   if (xc == 0) return false;
   const int nb = ((l.ny + TY - 1) / TY) * ((l.nz + TZ - 1) / TZ) * ((l.nx + xc - 1) / xc);
+  if (dots && nb > kPartCap) return false;
   constexpr int NT = MarchTile<T>::NT;
-  if (fine)
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 1>), dim3(nb), dim3(NT), 0, s, l,
-                       first_color, zero_init, xc);
+  if (dots)
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 1, 1>), dim3(nb), dim3(NT), 0, s, l,
+                       first_color, zero_init, xc, dots->sigma, dots->r, dots->q, dots->part);
+  else if (fine)
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 1, 0>), dim3(nb), dim3(NT), 0, s, l,
+                       first_color, zero_init, xc, 0.0, nullptr, nullptr, nullptr);
   else
-    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 0>), dim3(nb), dim3(NT), 0, s, l,
-                       first_color, zero_init, xc);
+    hipLaunchKernelGGL((k_rbgs_march<T, TY, TZ, NT, 0, 0>), dim3(nb), dim3(NT), 0, s, l,
+                       first_color, zero_init, xc, 0.0, nullptr, nullptr, nullptr);
   return true;
 }
 
@@ -2161,7 +2188,8 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
                                            T*);                                               \
   template void launch_coarsest_solve<T>(hipStream_t, const LevelK<T>&, const T*);            \
   template void launch_rbgs<T>(hipStream_t, const LevelK<T>&, int, int, int);                 \
-  template bool launch_rbgs_march<T>(hipStream_t, const LevelK<T>&, int, int, int, long long); \
+  template bool launch_rbgs_march<T>(hipStream_t, const LevelK<T>&, int, int, int, long long,   \
+                                     const SweepDots*);                                       \
   template bool rbgs_march_fits<T>(const LevelK<T>&, long long);                             \
   template bool launch_resid_restrict_march<T>(hipStream_t, const LevelK<T>&, const LevelK<T>&, \
                                                long long);                                    \
