@@ -42,8 +42,10 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
         "mg_residual_fine": 6 * T + T / 8,
         "restrict_fine": T + T / 8,
         "prolong_fine": T / 8 + 2 * T,
-        "pcg_direction": T + 7 * 8,         # zT, p, diag, 3 cf in; p, q out
-        "pcg_update": 6 * 8 + T,            # p, q, x, r in; x, r out; b out
+        # zT, p, x, diag, 3 cf in; p, q, x out (x += alpha p of the previous
+        # iteration is folded into the direction kernel)
+        "pcg_direction": T + 6 * 8 + 3 * 8,
+        "pcg_update": 3 * 8 + T,            # r, q in; r, b out
         "pcg_precond": T + 2 * 8,           # zT, r, q in (dot products only)
         "residual_schur": 8 * 8 + 2 * 8 + (T if T == 4 else 0),
         "local_solve": (12 if not iso else 8) * 8 + (7 if not iso else 4) * 8,
