@@ -24,10 +24,11 @@ Modules:
   analytic    Stromgren radius and the Shapiro-Giroux I-front law
   diagnostics I-front radius, budgets
   controller  adaptive time steps with the temporal accuracy tau_tol
+  advection   donor-cell advection of the step's fields (operator split, step (iv))
 
 Parity status of each function is stated in its module header.
 """
 from .constants import *  # noqa: F401,F403
-from . import grey, cosmology, rates, model, newton, adjoint, analytic, diagnostics, controller  # noqa: F401
+from . import grey, cosmology, rates, model, newton, adjoint, analytic, diagnostics, controller, advection  # noqa: F401
 from .model import Params, StepContext, params_from_workload, initial_state, source_field  # noqa: F401
 from .newton import step, run  # noqa: F401
