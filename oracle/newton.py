@@ -23,7 +23,9 @@ keeps every iterate admissible (0 <= n <= n_H, e > 0).
           S = J_EE - diag(J_En (B^-1 C)_n),  r = -f_E + J_En (B^-1 f_loc)_n
           S dE = r (sparse direct)
           backtracking: lambda = 1, 1/2, ... on E_k + lambda dE with the
-          local re-solve, until ||f|| <= (1 - 1e-4 lambda) ||f(U_k)||
+          local re-solve, until ||f|| <= (1 - 1e-4 lambda) ||f(U_k)||; a
+          trial whose local re-solve does not converge has no residual and
+          counts as no decrease (lambda is halved)
 
 Parity: pinned by the full-system solve against the Schur route (same
 Newton direction), by quadratic convergence of the iterates and by the
@@ -334,8 +336,14 @@ def step(p: M.Params, t_n: float, dt: float, nH, src, E, e, n, *, solver="schur"
         lam = 1.0
         for cut in range(p.ls_max_cuts + 1):
             Et = E + lam * dE
-            nt, et = local_solve(p, ctx, Et, n + lam * dn,
-                                 None if de is None else e + lam * de)
+            try:
+                nt, et = local_solve(p, ctx, Et, n + lam * dn,
+                                     None if de is None else e + lam * de)
+            except NewtonFailure:
+                # no local solution at this trial: no residual, so no decrease
+                lam *= 0.5
+                cuts_total += 1
+                continue
             ft = M.residual(p, ctx, Et, et, nt)
             nt_norm = M.norm(p, ctx, *ft)
             if nt_norm <= (1.0 - p.armijo * lam) * nrm:
