@@ -134,6 +134,13 @@ typedef struct rh_advance_stats {
   double change_last;          /* weighted change of the last accepted step              */
 } rh_advance_stats;
 
+/* Statistics of rh_advect (host memory). */
+typedef struct rh_advect_stats {
+  int32_t substeps;            /* donor-cell substeps taken                               */
+  double courant;              /* largest outgoing Courant number over the whole dt      */
+  double courant_substep;      /* the same per substep (<= cfl)                          */
+} rh_advect_stats;
+
 typedef struct rh_handle rh_handle;
 
 /* Fill p with the defaults (a 16^3 static zero-flux grid; every solver
@@ -194,6 +201,36 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n_s, double dt_s, const double*
 rh_status rh_advance(rh_handle* h, double t0_s, double t_end_s, double dt0_s, double tau_tol,
                      double dt_max_s, const double* nH, const double* src, double* E, double* e,
                      double* nHI, rh_advance_stats* stats, double* t_reached);
+
+/* Advect (nH, E, e, nHI) in place from t0_s to t0_s + dt_s with the
+ * prescribed velocity (vx, vy, vz): the part of the operator split's
+ * hydrodynamic step that moves the number densities and the radiation
+ * energy before the implicit step (Algorithm section, step (iv); equations
+ * enzo-chemical_ionization and enzo-cons_radiation: d_t q + (1/a) div(q v)
+ * = 0, comoving divergence, proper peculiar velocity).  Call rh_implicit_step
+ * on the advected fields afterwards to complete the split step.
+ *   - Velocities: cell-centred, cm/s, device FP64 fields like the others
+ *     (read only; must not alias the advected fields).  A face takes the
+ *     mean of its two cells; 0 at an RH_BC_ZEROFLUX wall (closed box); the
+ *     boundary cell's velocity at an RH_BC_OUTFLOW wall, where the ghost
+ *     cell repeats the boundary cell's values; periodic axes wrap.
+ *   - Conserved per cell: nH, E, nHI and nH * e (e is energy per unit
+ *     mass); e is recovered as (nH e) / nH.  e is neither read nor written
+ *     when isothermal (may be NULL then).
+ *   - Scheme: first-order donor-cell (upwind) fluxes, unsplit over the three
+ *     axes, in m equal substeps, m = max(1, ceil(C / cfl)) where C is the
+ *     largest outgoing Courant number of a cell (sum over its faces of
+ *     dt v_face / (a h) pointing out of it) at a(t0); each substep uses a at
+ *     its midpoint.  With cfl <= 1 every substep is a convex combination:
+ *     fields stay non-negative and e, nHI / nH stay within their
+ *     neighbours' range.
+ * 0 < cfl <= 1.  Uses the handle's workspace as scratch (not during another
+ * call on h).  Returns RH_ENONFINITE, fields untouched, when a velocity is
+ * not finite; RH_EINVAL when more than 2^20 substeps would be needed.
+ * The call synchronises its stream.  stats may be NULL. */
+rh_status rh_advect(rh_handle* h, double t0_s, double dt_s, const double* vx, const double* vy,
+                    const double* vz, double cfl, double* nH, double* E, double* e, double* nHI,
+                    rh_advect_stats* stats);
 
 /* Evaluate the residual f(U) of the step from U^n = (E_n, e_n, nHI_n) at
  * the state U = (E, e, nHI), exactly as rh_implicit_step does (face limiter
@@ -256,7 +293,8 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
  * correction update, 13 right-hand-side cast, 14 one colour of a sweep on
  * a finest level too small for the fused sweep, 15 the last fused sweep of
  * a V-cycle on the finest level when it also forms the conjugate-gradient
- * dot products (class 11 then has no launches).  ms / counts are host arrays
+ * dot products (class 11 then has no launches), 16 advection (rh_advect:
+ * Courant reduction and substeps).  ms / counts are host arrays
  * (either may be NULL); reset != 0 clears the totals afterwards. */
 rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
                                int32_t reset);

@@ -112,6 +112,12 @@ def advect(p: M.Params, t0: float, dt: float, v, nH, E, e, n, cfl: float = 0.9):
         raise ValueError("need dt > 0 and 0 < cfl <= 1")
     v = [np.asarray(c, dtype=np.float64) for c in v]
     m, _ = substeps(p, t0, dt, v, cfl)
+    return advect_substeps(p, t0, dt, m, v, nH, E, e, n), m
+
+
+def advect_substeps(p: M.Params, t0: float, dt: float, m: int, v, nH, E, e, n):
+    """The m substeps of advect over [t0, t0 + dt]; returns (nH, E, e, n)."""
+    v = [np.asarray(c, dtype=np.float64) for c in v]
     ds = dt / m
     nH = np.array(nH, dtype=np.float64)
     E = np.array(E, dtype=np.float64)
@@ -126,7 +132,7 @@ def advect(p: M.Params, t0: float, dt: float, v, nH, E, e, n, cfl: float = 0.9):
             nH1, E, n, rho_e = donor_step(p, v, [nH, E, n, nH * e], scale)
             e = rho_e / nH1
             nH = nH1
-    return (nH, E, e, n), m
+    return nH, E, e, n
 
 
 def split_step(p: M.Params, t0: float, dt: float, v, nH, src, E, e, n, cfl: float = 0.9,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "librh.so")
 KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rbgs_fine",
                   "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
                   "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast",
-                  "rbgs_fine_colour", "rbgs_fine_dots"]
+                  "rbgs_fine_colour", "rbgs_fine_dots", "advect"]
 
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",
@@ -74,6 +74,13 @@ class RhAdvanceStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RhAdvectStats(ctypes.Structure):
+    _fields_ = [("substeps", _i32), ("courant", _f64), ("courant_substep", _f64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # exported symbols and their signatures (name -> (restype, argtypes))
 _PP = ctypes.POINTER(RhParams)
 _SP = ctypes.POINTER(RhStepStats)
@@ -86,6 +93,8 @@ SIGNATURES = {
                                _vp, _vp, _vp, _vp, _vp, _SP]),
     "rh_advance": (_i32, [_vp, _f64, _f64, _f64, _f64, _f64, _vp, _vp, _vp, _vp, _vp,
                           ctypes.POINTER(RhAdvanceStats), ctypes.POINTER(_f64)]),
+    "rh_advect": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _f64, _vp, _vp, _vp, _vp,
+                         ctypes.POINTER(RhAdvectStats)]),
     "rh_residual": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, ctypes.POINTER(_f64)]),
     "rh_schur_solve": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

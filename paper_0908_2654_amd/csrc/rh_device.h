@@ -1,0 +1,75 @@
+// Device helpers shared by the kernel sources: wavefront and workgroup
+// reductions into the deterministic partial-sum layout, and the XCD-aware
+// tile order of the marching kernels.
+#ifndef RH_DEVICE_H
+#define RH_DEVICE_H
+
+#include <hip/hip_runtime.h>
+
+#include "rh_internal.h"
+
+namespace rh {
+
+__device__ inline void cell_ijk(long long idx, int ny, int nz, int& i, int& j, int& k) {
+  long long jk = idx % ((long long)ny * nz);
+  i = (int)(idx / ((long long)ny * nz));
+  j = (int)(jk / nz);
+  k = (int)(jk % nz);
+}
+
+__device__ inline long long cell_index(int i, int j, int k, int ny, int nz) {
+  return ((long long)i * ny + j) * nz + k;
+}
+
+// Block reductions over 256 threads (4 wavefronts of 64).
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int NV, int NTH = kBlock>
+__device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max)[NV],
+                                          const int (&slot)[NV], double* part) {
+  __shared__ double sh[NV][NTH / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double v = is_max[q] ? wave_max(vals[q]) : wave_sum(vals[q]);
+    if (lane == 0) sh[q][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double v = sh[q][0];
+      for (int w = 1; w < NTH / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
+      part[(long long)slot[q] * kPartCap + blockIdx.x] = v;
+      if (blockIdx.x == 0) part[(long long)RS_COUNT * kPartCap + slot[q]] = (double)gridDim.x;
+    }
+  }
+}
+
+inline int red_grid(long long N) {
+  long long g = (N + kBlock - 1) / kBlock;
+  return (int)(g < kRedBlocks ? (g < 1 ? 1 : g) : kRedBlocks);
+}
+
+__device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Give each XCD a contiguous range of tile indices, so tiles that share
+// halo cache lines (neighbours along z come next in tile order) run on the
+// same XCD at about the same time.  A bijection of [0, nb).
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int bid, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int xcd = bid % kXcds, k = bid / kXcds;
+  return xcd * q + min(xcd, r) + k;
+}
+
+}  // namespace rh
+
+#endif  // RH_DEVICE_H

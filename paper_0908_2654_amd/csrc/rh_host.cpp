@@ -245,7 +245,7 @@ struct StateBuf {
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
   KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_RBGS0D,
-  KK_COUNT
+  KK_ADVECT, KK_COUNT
 };
 
 struct rh_handle {
@@ -1098,6 +1098,73 @@ rh_status rh_advance(rh_handle* h, double t0, double t_end, double dt0, double t
   acc.dt_next = dt;
   if (stats) *stats = acc;
   if (t_reached) *t_reached = t;
+  return RH_OK;
+}
+
+rh_status rh_advect(rh_handle* h, double t0, double dt, const double* vx, const double* vy,
+                    const double* vz, double cfl, double* nH, double* E, double* e, double* nHI,
+                    rh_advect_stats* stats) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  rh_status st = check_ptrs(h, {vx, vy, vz, nH, E, nHI});
+  if (st != RH_OK) return st;
+  if (!iso && (st = check_ptrs(h, {e})) != RH_OK) return st;
+  if (!std::isfinite(t0) || !(dt > 0) || !std::isfinite(dt) || !(cfl > 0) || !(cfl <= 1))
+    return fail(h, RH_EINVAL, "need finite t0, dt > 0 and 0 < cfl <= 1");
+  AdvK a{};
+  a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz;
+  a.N = h->N;
+  for (int f = 0; f < 6; ++f) a.bc[f] = h->p.bc[f];
+  a.iso = iso ? 1 : 0;
+  a.v[0] = vx; a.v[1] = vy; a.v[2] = vz;
+  double a0, H0;
+  cosmo_at(h->p, t0, a0, H0);
+  a.scale = dt / (a0 * h->h);
+  {
+    Timed tm(h, KK_ADVECT);
+    launch_advect_courant(h->stream, a, h->part);
+  }
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, slot_bit(RS_COURANT) | slot_bit(RS_NONFINITE))) != RH_OK) return st;
+  const double C = h->hred[RS_COURANT];
+  if (h->hred[RS_NONFINITE] > 0 || !std::isfinite(C))
+    return fail(h, RH_ENONFINITE, "rh_advect: non-finite velocity or Courant number");
+  constexpr double kMaxSub = 1 << 20;
+  const double msub = std::max(1.0, std::ceil(C / cfl));
+  if (msub > kMaxSub) return fail(h, RH_EINVAL, "rh_advect: more than 2^20 substeps needed");
+  const int m = (int)msub;
+  const double ds = dt / m;
+  // ping-pong between the caller's fields (A) and workspace buffers (B),
+  // which are free between implicit steps
+  double* A[4] = {nH, E, nHI, iso ? nullptr : e};
+  double* B[4] = {h->dEa, h->B.E, h->B.n, iso ? nullptr : h->B.e};
+  for (int sub = 0; sub < m; ++sub) {
+    double a_mid, H_mid;
+    cosmo_at(h->p, t0 + (sub + 0.5) * ds, a_mid, H_mid);
+    a.scale = ds / (a_mid * h->h);
+    double* const* from = (sub & 1) ? B : A;
+    double* const* to = (sub & 1) ? A : B;
+    for (int q = 0; q < 4; ++q) {
+      a.qi[q] = from[q];
+      a.qo[q] = to[q];
+    }
+    Timed tm(h, KK_ADVECT);
+    launch_advect(h->stream, a);
+  }
+  HIPCHK(hipGetLastError());
+  if (m & 1) {
+    const size_t bytes = sizeof(double) * h->N;
+    for (int q = 0; q < (iso ? 3 : 4); ++q)
+      HIPCHK(hipMemcpyAsync(A[q], B[q], bytes, hipMemcpyDeviceToDevice, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->timing) flush_timing(h);
+  if (stats) {
+    stats->substeps = m;
+    stats->courant = C;
+    stats->courant_substep = C / m;
+  }
   return RH_OK;
 }
 

@@ -79,6 +79,7 @@ enum RedSlot {
   RS_ZQ,           // sum z.q
   RS_CHG2,         // sum of squared weighted changes U^{n+1} - U^n (step controller)
   RS_NEGE,         // max over cells of -E/E_s (positivity check)
+  RS_COURANT,      // max over cells of the outgoing Courant number (advection)
   RS_COUNT
 };
 static_assert(RS_COUNT <= 32, "slot masks are 32-bit");
@@ -208,6 +209,22 @@ void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double
 template <class T>
 void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
                         const double* q, double* part);
+
+// advection of the step's fields (operator split, step (iv)), rh_advect.hip
+struct AdvK {
+  int nx, ny, nz;
+  long long N;
+  int bc[6];
+  int iso;                  // 1: e is not advected
+  double scale;             // substep / (a h): face velocity -> face Courant number
+  const double* v[3];       // cell-centred proper peculiar velocity per axis
+  const double* qi[4];      // n_H, E, n_HI, e of the substep's start
+  double* qo[4];            // the same after the substep
+};
+// partial maxima of the outgoing Courant number per cell into RS_COURANT
+void launch_advect_courant(hipStream_t s, const AdvK& a, double* part);
+// one donor-cell substep qi -> qo (qo must not alias qi)
+void launch_advect(hipStream_t s, const AdvK& a);
 
 // adjoint step
 struct AdjArgs {

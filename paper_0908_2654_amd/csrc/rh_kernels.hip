@@ -9,59 +9,10 @@
 #include <cmath>
 #include <type_traits>
 
+#include "rh_device.h"
 #include "rh_internal.h"
 
 namespace rh {
-
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-__device__ inline void cell_ijk(long long idx, int ny, int nz, int& i, int& j, int& k) {
-  long long jk = idx % ((long long)ny * nz);
-  i = (int)(idx / ((long long)ny * nz));
-  j = (int)(jk / nz);
-  k = (int)(jk % nz);
-}
-
-__device__ inline long long cell_index(int i, int j, int k, int ny, int nz) {
-  return ((long long)i * ny + j) * nz + k;
-}
-
-// Block reductions over 256 threads (4 wavefronts of 64).
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ inline double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-template <int NV, int NTH = kBlock>
-__device__ inline void block_reduce_store(double (&vals)[NV], const int (&is_max)[NV],
-                                          const int (&slot)[NV], double* part) {
-  __shared__ double sh[NV][NTH / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double v = is_max[q] ? wave_max(vals[q]) : wave_sum(vals[q]);
-    if (lane == 0) sh[q][wid] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      double v = sh[q][0];
-      for (int w = 1; w < NTH / 64; ++w) v = is_max[q] ? fmax(v, sh[q][w]) : v + sh[q][w];
-      part[(long long)slot[q] * kPartCap + blockIdx.x] = v;
-      if (blockIdx.x == 0) part[(long long)RS_COUNT * kPartCap + slot[q]] = (double)gridDim.x;
-    }
-  }
-}
-
-inline int red_grid(long long N) {
-  long long g = (N + kBlock - 1) / kBlock;
-  return (int)(g < kRedBlocks ? (g < 1 ? 1 : g) : kRedBlocks);
-}
 
 // ---------------------------------------------------------------------------
 // face limiter (equation limiter, kappa_S = 0)
@@ -641,7 +592,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
   const int s = blockIdx.x;
   if (!((mask >> s) & 1u)) return;
   const bool is_max = (s == RS_RMAX || s == RS_LOCAL_FAIL || s == RS_LOCAL_ITS || s == RS_EMAX ||
-                       s == RS_SMAX || s == RS_NONFINITE || s == RS_BAD_RES || s == RS_NEGE);
+                       s == RS_SMAX || s == RS_NONFINITE || s == RS_BAD_RES || s == RS_NEGE ||
+                       s == RS_COURANT);
   const int nblocks =
       (int)fmin(fmax(part[(long long)RS_COUNT * kPartCap + s], 0.0), (double)kPartCap);
   double v = is_max ? -INFINITY : 0.0;
@@ -936,18 +888,6 @@ struct ResidTile<double> {
   static constexpr int TY = 8, TZ = 32, NT = 256;
 };
 
-__device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Give each XCD a contiguous range of tile indices, so tiles that share
-// halo cache lines (neighbours along z come next in tile order) run on the
-// same XCD at about the same time.  A bijection of [0, nb).
-constexpr int kXcds = 8;
-__device__ inline int xcd_tile(int bid, int nb) {
-  const int q = nb / kXcds, r = nb % kXcds;
-  const int xcd = bid % kXcds, k = bid / kXcds;
-  return xcd * q + min(xcd, r) + k;
-}
 
 //
 // DOTS: the sweep's output is the preconditioned residual z_T of the

@@ -10,7 +10,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import RhAdvanceStats, RhParams, RhStepStats, check, lib
+from ._lib import RhAdvanceStats, RhAdvectStats, RhParams, RhStepStats, check, lib
 
 _F64 = ctypes.c_double
 
@@ -158,6 +158,24 @@ class Solver:
         d = st.as_dict()
         d["t_reached"] = tr.value
         return d
+
+    def advect(self, t0, dt, v, nH, E, e, nHI, cfl=0.9) -> dict:
+        """Advect (nH, E, e, nHI) in place over [t0, t0 + dt] with the cell-centred
+        velocity v = (vx, vy, vz) (operator split, step (iv)); returns the
+        substep statistics."""
+        st = RhAdvectStats()
+        s = lib.rh_advect(self._h, float(t0), float(dt), _ptr(v[0]), _ptr(v[1]), _ptr(v[2]),
+                          float(cfl), _ptr(nH), _ptr(E), _ptr(e), _ptr(nHI), ctypes.byref(st))
+        check(s, self._h)
+        return st.as_dict()
+
+    def split_step(self, t0, dt, v, nH, src, E, e, nHI, cfl=0.9) -> dict:
+        """One operator-split step in place: advection over dt, then the
+        implicit step from the advected fields (steps (iv) and (v))."""
+        adv = self.advect(t0, dt, v, nH, E, e, nHI, cfl)
+        st = self.step(t0, dt, nH, src, E, e, nHI)
+        st["advect"] = adv
+        return st
 
     def residual(self, t, dt, nH, src, Un, U, want_fields=True):
         """f(U) of the step from U^n: returns (fE, fe, fn, norm)."""

@@ -266,6 +266,14 @@ def gaussian_random_field(dims, pk_index: float, seed: int) -> np.ndarray:
     return d
 
 
+def velocity_field(dims, v_rms: float, pk_index: float = -3.0, seed: int = 100):
+    """Seeded cell-centred peculiar velocity (vx, vy, vz) [cm/s]: three
+    independent periodic Gaussian random fields with P(k) ~ |k|^pk_index,
+    each scaled to standard deviation v_rms (compressive and rotational
+    parts alike; smooth on the grid scale for pk_index <= -3)."""
+    return tuple(v_rms * gaussian_random_field(dims, pk_index, seed + d) for d in range(3))
+
+
 def density_field(w: Workload) -> np.ndarray:
     """Comoving hydrogen number density n_H [cm^-3], shape dims, float64."""
     if w.density == "uniform":
