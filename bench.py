@@ -56,16 +56,13 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
 def measured_traffic(kind, workload):
     """HBM bytes per launch of `kind` from the committed counter record, or
     None when there is none or the kernels have changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload.split('_')[0]}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    src = os.path.join(ROOT, "paper_0908_2654_amd", "csrc", "rh_kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("class") != kind or rec.get("kernels_source_sha256") != sha:
+    from paper_0908_2654_amd.profile_summary import kernels_sha256
+    if rec.get("class") != kind or rec.get("kernels_source_sha256") != kernels_sha256():
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -137,6 +134,56 @@ def run_path(P, w, prec, inp, state, t_start, dt, steps, timing, adjoint=False):
     return wall, stats, kt, (E, e, n), adj
 
 
+ADV_V_RMS = 1.0e7   # cm/s per component: 100 km/s peculiar velocities
+ADV_SEED = 101
+
+
+def run_advection(P, w, inp, state, t, dt, reps=3):
+    """The operator split's advection step (rh_advect) on the same fields
+    with a seeded 100 km/s random velocity over the same dt: wall time of
+    whole calls, and the substep kernel's average launch time from the
+    library's events for its roofline (algorithmic bytes: n_H, E, n_HI, e and
+    three velocities read, four fields written)."""
+    import torch
+
+    import workloads as W
+    dev = inp["nH"].device
+    v = [torch.from_numpy(c).to(dev) for c in W.velocity_field(w.dims, ADV_V_RMS, seed=ADV_SEED)]
+    s = P.Solver(P.params_from_workload(w, precision=1), device=dev)
+    f = [inp["nH"].clone()] + [x.clone() for x in state]
+    nH, E, e, n = f
+    st = s.advect(t, dt, v, nH, E, e, n)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = s.advect(t, dt, v, nH, E, e, n)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    s.set_kernel_timing(True)
+    s.advect(t, dt, v, nH, E, e, n)
+    kt = s.kernel_timing()
+    s.set_kernel_timing(False)
+    s.close()
+    del v, f
+    N = w.ncells
+    ms_sub, cnt = kt["advect"][0] / kt["advect"][1], kt["advect"][1]
+    bpc = 72 if w.isothermal else 88
+    achieved = bpc * N / (ms_sub * 1e-3) / 1e9
+    traffic = measured_traffic("advect", w.name)
+    return {"ms_per_call": round(1e3 * wall, 3), "substeps": st["substeps"],
+            "courant": round(st["courant"], 4),
+            "Mcell_substeps_per_s": round(N * st["substeps"] / wall / 1e6, 1),
+            "v_rms_km_s": ADV_V_RMS / 1e5,
+            "courant_ms": round(kt["advect_courant"][0], 4),
+            "roofline": {"bound": "hbm", "kernel": "advect", "achieved": round(achieved, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                         "traffic_bytes_per_cell": None if traffic is None else round(traffic / N, 2),
+                         "bytes_per_cell": bpc, "avg_launch_ms": round(ms_sub, 4),
+                         "launches": cnt}}
+
+
 def cpu_baseline(w, nH_full, t0, dt, sub=64):
     """The oracle, as it stands, on a bounded sample: one implicit step of a
     sub^3 periodic sub-volume cut from the same workload (same cells, same
@@ -178,6 +225,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-advection", action="store_true",
+                    help="skip the operator split's advection step (rh_advect)")
     ap.add_argument("--mg-pre", type=int, default=2)
     ap.add_argument("--mg-post", type=int, default=2)
     ap.add_argument("--smoother", type=int, default=0,
@@ -272,6 +321,13 @@ def main():
     kernels = {k: {"ms_total": round(v[0], 2), "launches": v[1]} for k, v in kt_m.items() if v[1]}
     kernels["note"] = "first timed step, rerun with an event pair around every launch"
 
+    adv = None
+    if not args.no_advection:
+        adv = run_advection(P, w, inp, state, t_start, dt)
+        log(f"advection: {adv['ms_per_call']:.2f} ms per call, {adv['substeps']} substeps, "
+            f"{adv['roofline']['avg_launch_ms']:.3f} ms per substep "
+            f"({adv['roofline']['achieved']:.0f} GB/s algorithmic)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
@@ -300,6 +356,7 @@ def main():
         "roofline": roof,
         "adjoint": adj,
         "kernels_ms": kernels,
+        "advection": adv,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

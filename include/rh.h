@@ -293,8 +293,8 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
  * correction update, 13 right-hand-side cast, 14 one colour of a sweep on
  * a finest level too small for the fused sweep, 15 the last fused sweep of
  * a V-cycle on the finest level when it also forms the conjugate-gradient
- * dot products (class 11 then has no launches), 16 advection (rh_advect:
- * Courant reduction and substeps).  ms / counts are host arrays
+ * dot products (class 11 then has no launches), 16 advection substep
+ * (rh_advect), 17 its Courant-number reduction.  ms / counts are host arrays
  * (either may be NULL); reset != 0 clears the totals afterwards. */
 rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
                                int32_t reset);

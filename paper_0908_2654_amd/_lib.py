@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "librh.so")
 KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rbgs_fine",
                   "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
                   "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast",
-                  "rbgs_fine_colour", "rbgs_fine_dots", "advect"]
+                  "rbgs_fine_colour", "rbgs_fine_dots", "advect", "advect_courant"]
 
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",

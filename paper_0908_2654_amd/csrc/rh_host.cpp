@@ -245,7 +245,7 @@ struct StateBuf {
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
   KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_RBGS0D,
-  KK_ADVECT, KK_COUNT
+  KK_ADVECT, KK_ADVECT_C, KK_COUNT
 };
 
 struct rh_handle {
@@ -1122,7 +1122,7 @@ rh_status rh_advect(rh_handle* h, double t0, double dt, const double* vx, const 
   cosmo_at(h->p, t0, a0, H0);
   a.scale = dt / (a0 * h->h);
   {
-    Timed tm(h, KK_ADVECT);
+    Timed tm(h, KK_ADVECT_C);
     launch_advect_courant(h->stream, a, h->part);
   }
   HIPCHK(hipGetLastError());

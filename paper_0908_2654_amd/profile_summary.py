@@ -23,7 +23,17 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_0908_2654_amd", "csrc", "rh_kernels.hip")
+# the sources a traffic record depends on (its hash goes stale when they change)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0908_2654_amd", "csrc", f)
+               for f in ("rh_kernels.hip", "rh_advect.hip", "rh_device.h")]
+
+
+def kernels_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _short(name: str) -> str:
@@ -68,7 +78,7 @@ def traffic_record(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, kernel_
     write_scale = copy_bytes / (1024.0 * sum(cw) / len(cw))
     fk, wk = sum(f) / len(f), sum(w) / len(w)
     per_launch = 1024.0 * (fk * fetch_scale + wk * write_scale)
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    sha = kernels_sha256()
     return {
         "kernel": sorted(names)[0] if len(names) == 1 else sorted(names),
         "class": kind,

@@ -1,0 +1,127 @@
+"""Parity at the benchmark's full size: the 512^3 periodic reionisation
+volume (flat LCDM, z = 9, 4096 sources) in the launch configuration the
+benchmark times (mixed precision, conjugate gradients with the V(2,2)
+preconditioner, fused marching kernels on the finest level).  One implicit
+step runs on the GPU; the oracle then evaluates, cell by cell at sampled
+cells (source cells, the most ionised cells, random cells, corners),
+what the GPU evaluated for the whole grid:
+
+  * the residual f(U^{n+1}) of the GPU's solution (rh_residual), on a
+    periodic 3^3 block around the cell (the residual of a cell needs only
+    its face neighbours; the limiter floor R_min = 1/(a_n L_box) is the
+    whole box's);
+  * the Schur operator's row of the cell (rh_schur_operator): diagonal and
+    the six couplings;
+  * the step's own convergence: the GPU's RMS residual norm is below the
+    Newton tolerance and the oracle's sampled residuals are small.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import oracle_inputs, to_dev
+from oracle.constants import C_LIGHT
+
+pytestmark = pytest.mark.gpu
+
+
+def _cells(op, inp, n_src=16, n_front=16, n_rand=24, seed=3):
+    N0 = op.dims[0]
+    rng = np.random.default_rng(seed)
+    src_cells = np.argwhere(inp["src"] > 0)
+    pick = src_cells[rng.choice(len(src_cells), n_src, replace=False)]
+    cells = [tuple(int(v) for v in c) for c in pick]
+    cells += [(0, 0, 0), (N0 - 1, N0 - 1, N0 - 1), (0, N0 - 1, 5), (N0 - 1, 2, 0)]
+    cells += [tuple(int(v) for v in rng.integers(0, N0, 3)) for _ in range(n_rand)]
+    return cells, n_front
+
+
+def test_full_size_step_residual_and_operator_sampled(hip_device):
+    import paper_0908_2654_amd as P
+    w = W.get(4)
+    op, inp = oracle_inputs(w)
+    t0, dt = inp["t0"], inp["dt"]
+    prm = P.params_from_workload(w, precision=1)
+    assert prm.precision == 1 and prm.krylov == 1 and prm.mg_pre == 2 and prm.mg_post == 2
+    s = P.Solver(prm, device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    nH, src = d(inp["nH"]), d(inp["src"])
+    Un = tuple(d(inp[k]) for k in ("E", "e", "n"))
+    U = tuple(x.clone() for x in Un)
+    st = s.step(t0, dt, nH, src, *U)
+    print("step", {k: st[k] for k in ("newton_its", "lin_its_total", "res_final")})
+    fE, fe, fn, nrm = s.residual(t0, dt, nH, src, Un, U)
+    assert nrm <= w.newton_tol and nrm == pytest.approx(st["res_final"], rel=1e-6)
+    diag, cf = s.schur_operator(t0, dt, nH, src, Un, U)
+    s.close()
+    host = lambda X: X.cpu().numpy()  # noqa: E731
+    Uh = tuple(host(x) for x in U)
+    xh = 1.0 - Uh[2] / inp["nH"]
+    worst, sampled, ncells = check_cells(op, inp, Uh, (host(fE), host(fe), host(fn)), host(diag),
+                                         [host(c) for c in cf], xh)
+    print("cells", ncells, "parity", worst, "oracle residual at sampled cells", sampled)
+    assert worst["fE"] < 1e-12 and worst["fn"] < 1e-12 and worst["fe"] < 1e-12
+    assert worst["diag"] < 1e-12 and worst["off"] < 1e-12
+    # the step's solution solves the oracle's equations at the sampled cells
+    assert sampled["fE"] < 1e-5 and sampled["fn"] < 1e-5 and sampled["fe"] < 1e-5
+
+
+def check_cells(op, inp, U, f, diag, cf, xh):
+    """Largest differences between the given residual fields f = (fE, fe, fn)
+    and Schur operator (diag, cf) of state U and the oracle's, at sampled
+    cells (each on a periodic 3^3 block); and the oracle's residual there."""
+    from oracle import model as OM, newton as ON
+    fE, fe, fn = f
+    t0, dt = inp["t0"], inp["dt"]
+    N0 = op.dims[0]
+    cells, n_front = _cells(op, inp)
+    # the most ionised cells (after one step the H II regions are still
+    # smaller than a cell): 16 of the 64 with the largest x_HII
+    top = np.argpartition(xh.ravel(), -64)[-64:]
+    rng = np.random.default_rng(4)
+    cells += [tuple(int(v) for v in np.unravel_index(i, op.dims))
+              for i in rng.choice(top, n_front, replace=False)]
+    a_n = op.cosmo.a(t0)
+    bp = op.with_(dims=(3, 3, 3), box=3 * op.h, R_min=1.0 / (a_n * op.box))
+    worst = {"fE": 0.0, "fn": 0.0, "fe": 0.0, "diag": 0.0, "off": 0.0}
+    sampled = {"fE": 0.0, "fn": 0.0, "fe": 0.0}
+    E_s = max(float(inp["E"].max()), dt * float(inp["src"].max()), op.E_floor)
+    ctr = (1, 1, 1)
+    for c in cells:
+        idx = [np.arange(c[k] - 1, c[k] + 2) % N0 for k in range(3)]
+        cut = lambda X: X[np.ix_(*idx)]  # noqa: E731
+        nHb, srcb = cut(inp["nH"]), cut(inp["src"])
+        Enb, enb, nnb = cut(inp["E"]), cut(inp["e"]), cut(inp["n"])
+        Eb, eb, nb = (cut(x) for x in U)
+        ctx = OM.make_context(bp, t0, dt, nHb, srcb, Enb, enb, nnb)
+        fEo, feo, fno = OM.residual(bp, ctx, Eb, eb, nb)
+        # residual parity, relative to the size of the terms whose
+        # difference f_E is (E, E^n, dt src, dt c kappa E and the diffusion
+        # couplings dt sum_f cf_f E)
+        cfs = ctx.cf_1[0][ctr] + ctx.cf_1[0][2, 1, 1] + ctx.cf_1[1][ctr] + ctx.cf_1[1][1, 2, 1] \
+            + ctx.cf_1[2][ctr] + ctx.cf_1[2][1, 1, 2]
+        scaleE = np.abs(Eb).max() * (1.0 + dt * cfs) + abs(Enb[ctr]) + dt * srcb[ctr] \
+            + dt * C_LIGHT * op.grey["sigma_E"] * nb[ctr] / ctx.a_1 ** 3 * abs(Eb[ctr])
+        worst["fE"] = max(worst["fE"], abs(fE[c] - fEo[ctr]) / scaleE)
+        worst["fn"] = max(worst["fn"], abs(fn[c] - fno[ctr]) / nHb[ctr])
+        worst["fe"] = max(worst["fe"], abs(fe[c] - feo[ctr]) / eb[ctr])
+        sampled["fE"] = max(sampled["fE"], abs(fEo[ctr]) / E_s)
+        sampled["fn"] = max(sampled["fn"], abs(fno[ctr]) / nHb[ctr])
+        sampled["fe"] = max(sampled["fe"], abs(feo[ctr]) / enb[ctr])
+        # Schur operator row of the cell: diagonal and the six couplings
+        loc = ON.local_jacobian(bp, ctx, Eb, eb, nb)
+        JEE, JEn = ON.radiation_jacobian(bp, ctx, Eb, nb)
+        S = ON.schur_operator(bp, loc, JEE, JEn, feo, fno, fEo)[0].tocsr()
+        ci = np.ravel_multi_index(ctr, (3, 3, 3))
+        worst["diag"] = max(worst["diag"], abs(diag[c] - S[ci, ci]) / abs(S[ci, ci]))
+        for ax in range(3):
+            dn = list(c)
+            dn[ax] = (c[ax] - 1) % N0
+            bu, bd = [1, 1, 1], [1, 1, 1]
+            bu[ax], bd[ax] = 2, 0
+            ju = np.ravel_multi_index(bu, (3, 3, 3))
+            jd = np.ravel_multi_index(bd, (3, 3, 3))
+            ref = max(abs(S[ci, ju]), abs(S[ci, jd]), 1e-300)
+            worst["off"] = max(worst["off"], abs(-cf[ax][c] - S[ci, ju]) / ref,
+                               abs(-cf[ax][tuple(dn)] - S[ci, jd]) / ref)
+    return worst, sampled, len(cells)
