@@ -464,7 +464,10 @@ k_local(StepK k, LocalArgs a, double* __restrict__ part) {
           small = fmax(small, fabs(lam * de) / e);
         }
         if (!(small == small)) break;  // NaN
-        if (lam == 1.0 && small <= 1e-15) {
+        // an undamped step of relative size s leaves an error of order s^2
+        // (quadratic convergence of the 2x2 Newton iteration): after s <= 1e-9
+        // the iterate is at the root to rounding
+        if (lam == 1.0 && small <= 1e-9) {
           conv = true;
           break;
         }
