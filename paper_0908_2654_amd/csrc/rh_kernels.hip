@@ -1051,28 +1051,44 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
   // coefficients of p+2 into the other buffer
   fetch_x(xa + 1, A);
   fetch_c(xa, true, A);
+  constexpr int NW = (TY * TZ + NT - 1) / NT;  // written cells per thread and plane
   auto step = [&](int p, const Buf& now, Buf& ahead) {
     // in LDS: x planes p-2..p+1, coefficients of p-1 and p, x faces of p-2..p
     if (p + 3 <= xb + 1) fetch_x(p + 3, ahead);
     if (p + 2 <= xb) fetch_c(p + 2, true, ahead);
+    const int q = p - 1;
+    // r and q of the cells written below, in flight during both updates
+    double rpre[NW], qpre[NW];
+    if (DOTS && q >= xa) {
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int t = tid + k * NT;
+        const int gy = ty * TY + t / TZ, gz = tz * TZ + t % TZ;
+        const bool ok = t < TY * TZ && gy < l.ny && gz < l.nz;
+        const int P = ok ? q * plane + gy * l.nz + gz : 0;
+        rpre[k] = ok ? rv[P] : 0.0;
+        qpre[k] = (ok && qv) ? qv[P] : 0.0;
+      }
+    }
     update(std::integral_constant<int, NRED>(), p, first_color, 1, TY + 2, TZ + 2);
     __syncthreads();
-    const int q = p - 1;
     if (q >= xa) {
       update(std::integral_constant<int, NBLK>(), q, 1 - first_color, 2, TY, TZ);
       __syncthreads();
       const T* src = xs + pmod(q, 4) * PL;
-      for (int t = tid; t < TY * TZ; t += NT) {
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const int t = tid + k * NT;
         const int lz = t % TZ, ly = t / TZ;
         const int gy = ty * TY + ly, gz = tz * TZ + lz;
-        if (gy < l.ny && gz < l.nz) {
+        if (t < TY * TZ && gy < l.ny && gz < l.nz) {
           const int P = q * plane + gy * l.nz + gz;
           const T v = src[(ly + 2) * HZ + lz + 2];
           l.x2[P] = v;
           if (DOTS) {
             const double zv = sigma * (double)v;
-            zr += zv * rv[P];
-            if (qv) zq += zv * qv[P];
+            zr += zv * rpre[k];
+            if (qv) zq += zv * qpre[k];
           }
         }
       }
