@@ -101,8 +101,9 @@ typedef struct rh_params {
                                /* defect correction x += V(b - S x)                      */
   int32_t smoother;            /* multigrid kernel form: 0 = auto (the red-black sweep   */
                                /* as one marching launch for both colours, and the       */
-                               /* residual fused with the restriction, on levels with    */
-                               /* >= 2048 of their tiles; elsewhere one launch per       */
+                               /* residual fused with the restriction, on levels where   */
+                               /* they get >= 2048 workgroups (the sweep below the       */
+                               /* finest level: >= 512); elsewhere one launch per        */
                                /* colour and separate residual and restriction), 1 =     */
                                /* always the separate launches, 2 = the marching         */
                                /* launches on every level their tiles fit (FP32 levels:  */

@@ -574,8 +574,10 @@ rh_status coarse_setup(rh_handle* h) {
 template <class T>
 void sweep(rh_handle* h, int l, int first_color, int zero_init, bool last = false) {
   LevelK<T>* L = levels<T>(h);
-  // auto: the fused sweep only where it gets enough workgroups to fill the chip
-  const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
+  // auto: the fused sweep only where it gets enough workgroups to fill the
+  // chip (below the finest level fewer, longer chunks: less re-staging of
+  // each chunk's boundary planes)
+  const long long min_tiles = h->p.smoother == 2 ? 1 : (l == 0 ? 2048 : 512);
   if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
     const bool dots = l == 0 && last && h->dots_wanted;
     if (dots) {
