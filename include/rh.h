@@ -227,7 +227,8 @@ rh_status rh_advance(rh_handle* h, double t0_s, double t_end_s, double dt0_s, do
  *     neighbours' range.
  * 0 < cfl <= 1.  Uses the handle's workspace as scratch (not during another
  * call on h).  Returns RH_ENONFINITE, fields untouched, when a velocity is
- * not finite; RH_EINVAL when more than 2^20 substeps would be needed.
+ * not finite; RH_EINVAL when more than 2^20 substeps would be needed or when
+ * two advected fields, or a velocity and a field, are the same array.
  * The call synchronises its stream.  stats may be NULL. */
 rh_status rh_advect(rh_handle* h, double t0_s, double dt_s, const double* vx, const double* vy,
                     const double* vz, double cfl, double* nH, double* E, double* e, double* nHI,

@@ -107,7 +107,162 @@ __global__ void __launch_bounds__(kBlock) k_advect_courant(AdvK a, double* __res
   block_reduce_store<2>(v, im, sl, part);
 }
 
+// The same reduction marching along x in the tiles of k_advect_march: each
+// velocity is read once per block (plus the tile's ring), the y and z
+// components of the current plane from LDS.
+constexpr int kCouTY = 8, kCouTZ = 64, kCouXC = 32;
+
+__global__ void __launch_bounds__(kBlock) k_advect_courant_march(AdvK a, int xc,
+                                                                double* __restrict__ part) {
+  constexpr int TY = kCouTY, TZ = kCouTZ, HZ = TZ + 2, PL = (TY + 2) * HZ;
+  constexpr int NR = TY / (kBlock / 64);
+  constexpr int NRING = 2 * TZ + 2 * TY;
+  static_assert(TZ == 64 && NRING <= kBlock, "one wave per row, one ring cell per thread");
+  __shared__ double svy[2][PL], svz[2][PL];
+  const int per[3] = {a.bc[0] == RH_BC_PERIODIC, a.bc[2] == RH_BC_PERIODIC,
+                      a.bc[4] == RH_BC_PERIODIC};
+  const int ntz = (a.nz + TZ - 1) / TZ, nty = (a.ny + TY - 1) / TY;
+  int bid = xcd_tile(blockIdx.x, gridDim.x);
+  const int tz = bid % ntz;
+  bid /= ntz;
+  const int ty = bid % nty;
+  const int cx = bid / nty;
+  const int ya = ty * TY, za = tz * TZ;
+  const int xa = cx * xc, xb = min(xa + xc, a.nx);
+  const long long plane = (long long)a.ny * a.nz;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  auto off2 = [&](int gy, int gz) -> int {
+    const int wy = adv_wrap(gy, a.ny, per[1]), wz = adv_wrap(gz, a.nz, per[2]);
+    return (wy >= 0 && wz >= 0) ? wy * a.nz + wz : -1;
+  };
+  int own[NR], li[NR];
+  bool real[NR], hym[NR], hyp[NR], hzm[NR], hzp[NR];
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    const int ly = wid + (kBlock / 64) * m, gy = ya + ly, gz = za + lane;
+    real[m] = gy < a.ny && gz < a.nz;
+    own[m] = off2(gy, gz);
+    hym[m] = off2(gy - 1, gz) >= 0;
+    hyp[m] = off2(gy + 1, gz) >= 0;
+    hzm[m] = off2(gy, gz - 1) >= 0;
+    hzp[m] = off2(gy, gz + 1) >= 0;
+    li[m] = (ly + 1) * HZ + lane + 1;
+  }
+  int r_off = -1, r_li = -1, r_axis = 1;
+  if (threadIdx.x < NRING) {
+    const int e = threadIdx.x;
+    int ly, lz;
+    if (e < 2 * TZ) {
+      ly = e < TZ ? 0 : TY + 1;
+      lz = e % TZ + 1;
+    } else {
+      const int f = e - 2 * TZ;
+      ly = f % TY + 1;
+      lz = f < TY ? 0 : TZ + 1;
+      r_axis = 2;
+    }
+    r_li = ly * HZ + lz;
+    r_off = off2(ya + ly - 1, za + lz - 1);
+  }
+  auto fetch = [&](int p, int off, int d) -> double {
+    const int gx = adv_wrap(p, a.nx, per[0]);
+    return (gx >= 0 && off >= 0) ? a.v[d][gx * plane + off] : 0.0;
+  };
+  double vxm[NR], vxc[NR], vxn[NR], vyn[NR], vzn[NR], vxo[NR], vyo[NR], vzo[NR];
+  double ring1 = 0.0, ring2 = 0.0;
+  {
+    const int b0 = xa & 1;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      vxm[m] = fetch(xa - 1, own[m], 0);
+      vxc[m] = fetch(xa, own[m], 0);
+      svy[b0][li[m]] = fetch(xa, own[m], 1);
+      svz[b0][li[m]] = fetch(xa, own[m], 2);
+      vxn[m] = fetch(xa + 1, own[m], 0);
+      vyn[m] = fetch(xa + 1, own[m], 1);
+      vzn[m] = fetch(xa + 1, own[m], 2);
+    }
+    if (r_li >= 0) {
+      const double v0 = fetch(xa, r_off, r_axis);
+      if (r_axis == 1) svy[b0][r_li] = v0; else svz[b0][r_li] = v0;
+      ring1 = fetch(xa + 1, r_off, r_axis);
+    }
+  }
+  __syncthreads();
+  double cmax = 0.0, bad = 0.0;
+  for (int x = xa; x < xb; ++x) {
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      if (x + 2 <= xb) {
+        vxo[m] = fetch(x + 2, own[m], 0);
+        vyo[m] = fetch(x + 2, own[m], 1);
+        vzo[m] = fetch(x + 2, own[m], 2);
+      }
+    }
+    if (r_li >= 0 && x + 2 < xb) ring2 = fetch(x + 2, r_off, r_axis);
+    const int b = x & 1;
+    const bool hxm = adv_wrap(x - 1, a.nx, per[0]) >= 0;
+    const bool hxp = adv_wrap(x + 1, a.nx, per[0]) >= 0;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      if (!real[m]) continue;
+      const int t = li[m];
+      const double vy = svy[b][t], vz = svz[b][t];
+      if (!isfinite(vxc[m]) || !isfinite(vy) || !isfinite(vz)) bad = 1.0;
+      double ud, uu, sc = 0.0;
+      face_courant(vxc[m], vxm[m], vxn[m], hxm, hxp, a.bc[0], a.bc[1], a.scale, ud, uu);
+      sc += fmax(uu, 0.0) + fmax(-ud, 0.0);
+      face_courant(vy, svy[b][t - HZ], svy[b][t + HZ], hym[m], hyp[m], a.bc[2], a.bc[3],
+                   a.scale, ud, uu);
+      sc += fmax(uu, 0.0) + fmax(-ud, 0.0);
+      face_courant(vz, svz[b][t - 1], svz[b][t + 1], hzm[m], hzp[m], a.bc[4], a.bc[5], a.scale,
+                   ud, uu);
+      sc += fmax(uu, 0.0) + fmax(-ud, 0.0);
+      cmax = fmax(cmax, sc);
+    }
+    if (x + 1 < xb) {
+      const int b1 = b ^ 1;
+#pragma unroll
+      for (int m = 0; m < NR; ++m) {
+        svy[b1][li[m]] = vyn[m];
+        svz[b1][li[m]] = vzn[m];
+      }
+      if (r_li >= 0) {
+        if (r_axis == 1) svy[b1][r_li] = ring1; else svz[b1][r_li] = ring1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      vxm[m] = vxc[m];
+      vxc[m] = vxn[m];
+      if (x + 2 <= xb) {
+        vxn[m] = vxo[m];
+        vyn[m] = vyo[m];
+        vzn[m] = vzo[m];
+      }
+    }
+    ring1 = ring2;
+  }
+  double v[2] = {cmax, bad};
+  const int im[2] = {1, 1};
+  const int sl[2] = {RS_COURANT, RS_NONFINITE};
+  block_reduce_store<2>(v, im, sl, part);
+}
+
 void launch_advect_courant(hipStream_t s, const AdvK& a, double* part) {
+  const int nty = (a.ny + kCouTY - 1) / kCouTY, ntz = (a.nz + kCouTZ - 1) / kCouTZ;
+  const long long tiles = (long long)nty * ntz;
+  if (a.nz >= kCouTZ && a.ny >= kCouTY && a.nx >= 2) {
+    int ncx = (a.nx + kCouXC - 1) / kCouXC;
+    const int xc = (a.nx + ncx - 1) / ncx;
+    ncx = (a.nx + xc - 1) / xc;
+    if (tiles * ncx <= kPartCap) {
+      hipLaunchKernelGGL(k_advect_courant_march, dim3((unsigned)(tiles * ncx)), dim3(kBlock), 0,
+                         s, a, xc, part);
+      return;
+    }
+  }
   hipLaunchKernelGGL(k_advect_courant, dim3(red_grid(a.N)), dim3(kBlock), 0, s, a, part);
 }
 

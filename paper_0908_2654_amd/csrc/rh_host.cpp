@@ -1114,6 +1114,17 @@ rh_status rh_advect(rh_handle* h, double t0, double dt, const double* vx, const 
   if (!iso && (st = check_ptrs(h, {e})) != RH_OK) return st;
   if (!std::isfinite(t0) || !(dt > 0) || !std::isfinite(dt) || !(cfl > 0) || !(cfl <= 1))
     return fail(h, RH_EINVAL, "need finite t0, dt > 0 and 0 < cfl <= 1");
+  {
+    const void* fields[4] = {nH, E, nHI, iso ? nullptr : e};
+    const void* vel[3] = {vx, vy, vz};
+    for (int i = 0; i < 4; ++i)
+      for (int j = i + 1; j < 4; ++j)
+        if (fields[i] && fields[i] == fields[j])
+          return fail(h, RH_EINVAL, "rh_advect: the advected fields must be distinct arrays");
+    for (const void* v : vel)
+      for (const void* f : fields)
+        if (f && v == f) return fail(h, RH_EINVAL, "rh_advect: a velocity aliases an advected field");
+  }
   AdvK a{};
   a.nx = h->p.nx; a.ny = h->p.ny; a.nz = h->p.nz;
   a.N = h->N;

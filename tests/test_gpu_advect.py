@@ -199,6 +199,10 @@ def test_advect_error_paths(hip_device):
     for a, b in zip(f, keep):
         assert torch.equal(a, b)
     v[1][3, 4, 5] = 0.0
+    for vv, ff in (([v[0], f[1], v[2]], f), (v, [f[0], f[0], f[2], f[3]])):
+        with pytest.raises(P.RhError) as ei:              # aliasing arrays
+            s.advect(0.0, 1.0, vv, *ff)
+        assert "RH_EINVAL" in str(ei.value)
     for cfl, dt in ((0.0, 1.0), (1.5, 1.0), (0.5, 0.0), (0.5, -1.0)):
         with pytest.raises(P.RhError) as ei:
             s.advect(0.0, dt, v, *f, cfl=cfl)
