@@ -72,8 +72,10 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
   double emax = 0.0, smax = 0.0, bad = 0.0;
   double* cfo[3] = {cfx, cfy, cfz};
   float* c32[3] = {c32x, c32y, c32z};
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
-       idx += (long long)blockDim.x * gridDim.x) {
+  // blocks of one XCD take consecutive cells, so the y neighbours a block
+  // reads were loaded by its neighbours on the same XCD (shared L2)
+  for (long long idx = xcd_tile(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x;
+       idx < k.N; idx += (long long)blockDim.x * gridDim.x) {
     int c[3];
     cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
     const double EP = En[idx];
@@ -535,8 +537,10 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
   const double dth = k.dt * k.theta;
   const double kfac_n = k.sigma_E / (k.a_n * k.a_n * k.a_n);
   double sfe = 0.0, rmax = 0.0, bad = 0.0;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < k.N;
-       idx += (long long)blockDim.x * gridDim.x) {
+  // blocks of one XCD take consecutive cells, so the y neighbours a block
+  // reads were loaded by its neighbours on the same XCD (shared L2)
+  for (long long idx = xcd_tile(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x;
+       idx < k.N; idx += (long long)blockDim.x * gridDim.x) {
     int c[3];
     cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
     const double EP = a.E[idx];
