@@ -125,3 +125,56 @@ def check_cells(op, inp, U, f, diag, cf, xh):
             worst["off"] = max(worst["off"], abs(-cf[ax][c] - S[ci, ju]) / ref,
                                abs(-cf[ax][tuple(dn)] - S[ci, jd]) / ref)
     return worst, sampled, len(cells)
+
+
+def test_full_size_adjoint_matches_finite_differences(hip_device):
+    """The adjoint of one step at 512^3 (mixed path) against central finite
+    differences of the forward step, for J = mean x_HII: the directional
+    derivatives along random one-signed perturbations of the source
+    strengths (steps of 1%) and of n_H (steps of 0.05%) (a property that holds at any size; the oracle's transpose solve
+    does not fit this grid).  Newton converges to 1e-11 on every forward
+    step so that the differences resolve the change of J."""
+    import torch
+
+    import paper_0908_2654_amd as P
+    w = W.get(4)
+    op, inp = oracle_inputs(w)
+    t0, dt = inp["t0"], inp["dt"]
+    s = P.Solver(P.params_from_workload(w, precision=1, newton_tol=1e-11), device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    nH, src = d(inp["nH"]), d(inp["src"])
+    U0 = tuple(d(inp[k]) for k in ("E", "e", "n"))
+    N = float(op.ncells)
+
+    def J(src_, nH_):
+        U = tuple(x.clone() for x in U0)
+        s.step(t0, dt, nH_, src_, *U)
+        return float((1.0 - U[2] / nH_).sum().item() / N), U
+
+    J0, U1 = J(src, nH)
+    lE = torch.zeros_like(nH)
+    le = torch.zeros_like(nH)
+    ln = -1.0 / (N * nH)
+    g_src = torch.zeros_like(nH)
+    g_nH = torch.zeros_like(nH)
+    s.adjoint_step(t0, dt, nH, src, U0, U1, (lE, le, ln), g_src, g_nH)
+    g_nH_total = g_nH + U1[2] / (N * nH * nH)      # J's own dependence on n_H
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    # one-signed directions (0.5..1.5 of each value): the change of J does not cancel
+    u_src = (0.5 + torch.rand(op.dims, generator=gen, dtype=torch.float64)).to(hip_device)
+    u_nH = (0.5 + torch.rand(op.dims, generator=gen, dtype=torch.float64)).to(hip_device)
+    # step sizes: 1% of the sources; for n_H below the initial ionised
+    # fraction (1.2e-3), so that n_HI^n <= n_H stays true
+    results = {}
+    for name, base, u, g, h in (("src", src, u_src, g_src, 1e-2),
+                                ("nH", nH, u_nH, g_nH_total, 5e-4)):
+        delta = base * u
+        Jp = J(src + h * delta, nH)[0] if name == "src" else J(src, nH + h * delta)[0]
+        Jm = J(src - h * delta, nH)[0] if name == "src" else J(src, nH - h * delta)[0]
+        fd = (Jp - Jm) / (2.0 * h)
+        adj = float((g * delta).sum().item())
+        results[name] = (adj, fd, abs(adj - fd) / abs(fd))
+    s.close()
+    print("J", J0, "directional derivatives (adjoint, finite difference, rel)", results)
+    for name, (adj, fd, rel) in results.items():
+        assert rel < 2e-3, (name, adj, fd, rel)
