@@ -177,4 +177,4 @@ def test_full_size_adjoint_matches_finite_differences(hip_device):
     s.close()
     print("J", J0, "directional derivatives (adjoint, finite difference, rel)", results)
     for name, (adj, fd, rel) in results.items():
-        assert rel < 2e-3, (name, adj, fd, rel)
+        assert rel < 1e-5, (name, adj, fd, rel)
