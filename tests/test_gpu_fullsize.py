@@ -1,10 +1,12 @@
-"""Parity at the benchmark's full size: the 512^3 periodic reionisation
-volume (flat LCDM, z = 9, 4096 sources) in the launch configuration the
-benchmark times (mixed precision, conjugate gradients with the V(2,2)
-preconditioner, fused marching kernels on the finest level).  One implicit
-step runs on the GPU; the oracle then evaluates, cell by cell at sampled
-cells (source cells, the most ionised cells, random cells, corners),
-what the GPU evaluated for the whole grid:
+"""Parity at the benchmark workloads' full sizes: the 64^3 EdS sphere, the
+128^3 and 256^3 lognormal volumes and the 512^3 periodic reionisation
+volume (flat LCDM, z = 9, 4096 sources), the last in the launch
+configuration the benchmark times (mixed precision, conjugate gradients
+with the V(2,2) preconditioner, fused marching kernels on the finest
+level).  One implicit step runs on the GPU; the oracle then evaluates, cell
+by cell at sampled cells (source cells, the most ionised cells, random
+cells, corners; away from walls on walled axes), what the GPU evaluated
+for the whole grid:
 
   * the residual f(U^{n+1}) of the GPU's solution (rh_residual), on a
     periodic 3^3 block around the cell (the residual of a cell needs only
@@ -25,24 +27,37 @@ from oracle.constants import C_LIGHT
 pytestmark = pytest.mark.gpu
 
 
+def _ranges(op):
+    """Sampled index range per axis: all cells on periodic axes, the interior
+    ones on walled axes (there a periodic 3^3 cut is a cell's true neighbourhood)."""
+    return [(0, n) if op.bc[2 * d] == 1 else (1, n - 1) for d, n in enumerate(op.dims)]
+
+
 def _cells(op, inp, n_src=16, n_front=16, n_rand=24, seed=3):
-    N0 = op.dims[0]
     rng = np.random.default_rng(seed)
-    src_cells = np.argwhere(inp["src"] > 0)
-    pick = src_cells[rng.choice(len(src_cells), n_src, replace=False)]
-    cells = [tuple(int(v) for v in c) for c in pick]
-    cells += [(0, 0, 0), (N0 - 1, N0 - 1, N0 - 1), (0, N0 - 1, 5), (N0 - 1, 2, 0)]
-    cells += [tuple(int(v) for v in rng.integers(0, N0, 3)) for _ in range(n_rand)]
+    rg = _ranges(op)
+    inside = lambda c: all(lo <= c[d] < hi for d, (lo, hi) in enumerate(rg))  # noqa: E731
+    src_cells = [c for c in np.argwhere(inp["src"] > 0) if inside(c)]
+    pick = rng.choice(len(src_cells), min(n_src, len(src_cells)), replace=False)
+    cells = [tuple(int(v) for v in src_cells[i]) for i in pick]
+    (a0, b0), (a1, b1), (a2, b2) = rg
+    cells += [(a0, a1, a2), (b0 - 1, b1 - 1, b2 - 1), (a0, b1 - 1, a2 + 5), (b0 - 1, a1 + 2, a2)]
+    cells += [tuple(int(rng.integers(lo, hi)) for lo, hi in rg) for _ in range(n_rand)]
     return cells, n_front
 
 
-def test_full_size_step_residual_and_operator_sampled(hip_device):
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_full_size_step_residual_and_operator_sampled(hip_device, cfg):
+    """Each benchmark workload at its own size and precision (64^3 EdS FP64
+    sphere, 128^3 and 256^3 lognormal volumes, and the 512^3 reionisation
+    volume in exactly the benchmark's launch configuration)."""
     import paper_0908_2654_amd as P
-    w = W.get(4)
+    w = W.get(cfg)
     op, inp = oracle_inputs(w)
     t0, dt = inp["t0"], inp["dt"]
-    prm = P.params_from_workload(w, precision=1)
-    assert prm.precision == 1 and prm.krylov == 1 and prm.mg_pre == 2 and prm.mg_post == 2
+    prm = P.params_from_workload(w)
+    if cfg == 4:
+        assert prm.precision == 1 and prm.krylov == 1 and prm.mg_pre == 2 and prm.mg_post == 2
     s = P.Solver(prm, device=hip_device)
     d = lambda a: to_dev(a, hip_device)  # noqa: E731
     nH, src = d(inp["nH"]), d(inp["src"])
@@ -59,7 +74,7 @@ def test_full_size_step_residual_and_operator_sampled(hip_device):
     xh = 1.0 - Uh[2] / inp["nH"]
     worst, sampled, ncells = check_cells(op, inp, Uh, (host(fE), host(fe), host(fn)), host(diag),
                                          [host(c) for c in cf], xh)
-    print("cells", ncells, "parity", worst, "oracle residual at sampled cells", sampled)
+    print(w.name, "cells", ncells, "parity", worst, "oracle residual at sampled cells", sampled)
     assert worst["fE"] < 1e-12 and worst["fn"] < 1e-12 and worst["fe"] < 1e-12
     assert worst["diag"] < 1e-12 and worst["off"] < 1e-12
     # the step's solution solves the oracle's equations at the sampled cells
@@ -73,22 +88,25 @@ def check_cells(op, inp, U, f, diag, cf, xh):
     from oracle import model as OM, newton as ON
     fE, fe, fn = f
     t0, dt = inp["t0"], inp["dt"]
-    N0 = op.dims[0]
+    dims = op.dims
     cells, n_front = _cells(op, inp)
     # the most ionised cells (after one step the H II regions are still
     # smaller than a cell): 16 of the 64 with the largest x_HII
-    top = np.argpartition(xh.ravel(), -64)[-64:]
+    rg = _ranges(op)
+    sl = tuple(slice(lo, hi) for lo, hi in rg)
+    xin = xh[sl]
+    top = np.argpartition(xin.ravel(), -64)[-64:]
     rng = np.random.default_rng(4)
-    cells += [tuple(int(v) for v in np.unravel_index(i, op.dims))
+    cells += [tuple(int(v) + lo for v, (lo, _) in zip(np.unravel_index(i, xin.shape), rg))
               for i in rng.choice(top, n_front, replace=False)]
     a_n = op.cosmo.a(t0)
-    bp = op.with_(dims=(3, 3, 3), box=3 * op.h, R_min=1.0 / (a_n * op.box))
+    bp = op.with_(dims=(3, 3, 3), box=3 * op.h, R_min=1.0 / (a_n * op.box), bc=(1,) * 6)
     worst = {"fE": 0.0, "fn": 0.0, "fe": 0.0, "diag": 0.0, "off": 0.0}
     sampled = {"fE": 0.0, "fn": 0.0, "fe": 0.0}
     E_s = max(float(inp["E"].max()), dt * float(inp["src"].max()), op.E_floor)
     ctr = (1, 1, 1)
     for c in cells:
-        idx = [np.arange(c[k] - 1, c[k] + 2) % N0 for k in range(3)]
+        idx = [np.arange(c[k] - 1, c[k] + 2) % dims[k] for k in range(3)]
         cut = lambda X: X[np.ix_(*idx)]  # noqa: E731
         nHb, srcb = cut(inp["nH"]), cut(inp["src"])
         Enb, enb, nnb = cut(inp["E"]), cut(inp["e"]), cut(inp["n"])
@@ -116,7 +134,7 @@ def check_cells(op, inp, U, f, diag, cf, xh):
         worst["diag"] = max(worst["diag"], abs(diag[c] - S[ci, ci]) / abs(S[ci, ci]))
         for ax in range(3):
             dn = list(c)
-            dn[ax] = (c[ax] - 1) % N0
+            dn[ax] = (c[ax] - 1) % dims[ax]
             bu, bd = [1, 1, 1], [1, 1, 1]
             bu[ax], bd[ax] = 2, 0
             ju = np.ravel_multi_index(bu, (3, 3, 3))
