@@ -216,6 +216,25 @@ def cpu_baseline(w, nH_full, t0, dt, sub=64):
     }
 
 
+def copy_bandwidth(dev, reps=5):
+    """GB/s of a plain 1 GiB device-to-device copy (bytes read + written per
+    second): the practical HBM ceiling of the box, for context."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +287,8 @@ def main():
     inp = device_inputs(w, s0, nH_host=nH_host)
     t0, dt, nsteps = schedule(w, prm)
     log(f"inputs ready in {time.perf_counter() - tg:.1f} s; dt = {dt:.4e} s")
+    copy_gbs = copy_bandwidth(dev)
+    log(f"plain device copy: {copy_gbs:.0f} GB/s")
     state = [inp["E"], inp["e"], inp["nHI"]]
     for k in range(args.warmup):
         st = s0.step(t0 + k * dt, dt, inp["nH"], inp["src"], *state)
@@ -314,6 +335,7 @@ def main():
     traffic = measured_traffic(kind, w.name)
     roof = {"bound": "hbm", "kernel": kind, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
             "traffic": None if traffic is None else round(traffic / 1e9, 3),
             "traffic_unit": "GB per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "traffic_bytes_per_cell": None if traffic is None else round(traffic / N, 2),
@@ -324,6 +346,8 @@ def main():
     adv = None
     if not args.no_advection:
         adv = run_advection(P, w, inp, state, t_start, dt)
+        adv["roofline"]["copy_GBs"] = round(copy_gbs, 1)
+        adv["roofline"]["frac_of_copy"] = round(adv["roofline"]["achieved"] / copy_gbs, 4)
         log(f"advection: {adv['ms_per_call']:.2f} ms per call, {adv['substeps']} substeps, "
             f"{adv['roofline']['avg_launch_ms']:.3f} ms per substep "
             f"({adv['roofline']['achieved']:.0f} GB/s algorithmic)")
