@@ -126,10 +126,10 @@ class Workload:
 
 # ---------------------------------------------------------------------------
 # The five benchmark workloads.  Stated values come from the workload
-# descriptions; values they leave open are fixed here (see the design doc for the
-# readings: box and dt of the static lognormal runs, EdS h=0.5, blackbody
-# spectrum whenever photoheating is on, periodic boundaries for the
-# lognormal fields, zero-flux walls for the single-source spheres).
+# descriptions; the values they leave open are fixed here: box and dt of the
+# static lognormal runs, EdS h = 0.5, a blackbody spectrum whenever
+# photoheating is on, periodic boundaries for the lognormal fields, zero-flux
+# walls for the single-source spheres.
 # ---------------------------------------------------------------------------
 CONFIGS = {
     0: Workload(
