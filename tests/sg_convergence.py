@@ -1,4 +1,4 @@
-"""Shapiro-Giroux verification study (run on a GPU machine; prints a table).
+"""Shapiro-Giroux verification study (needs an MI355X; prints a table).
 
 For each of the four rows of the verification section's cosmology table,
 advance the GPU solver (rh_advance: theta = 0.51, tau_tol = 1e-3) from z0 to
