@@ -1,0 +1,30 @@
+"""The benchmark's command-line contract that needs no GPU: more than one
+GPU is refused with a message (there is no multi-GPU path), and the
+algorithmic byte counts of the kernel classes are the documented ones."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_per_cell():
+    sys.path.insert(0, ROOT)
+    import bench
+    T = 4
+    b = bench.algorithmic_bytes_per_cell
+    assert b("rbgs_fine", T) == 28                 # x, b, diag, 3 faces in; x out
+    assert b("rbgs_fine_dots", T) == 44            # + r, q (FP64)
+    assert b("mg_residual_fine", T) == 24.5        # 6 fields in, coarse rhs out
+    assert b("pcg_direction", T) == 76             # zT, p, x, diag, 3 faces in; p, q, x out
+    assert b("pcg_update", T) == 28                # r, q in; r, b out
+    assert b("local_solve", T) == 152 and b("local_solve", T, iso=True) == 96
+    assert b("no_such_kernel", T) is None
