@@ -264,14 +264,15 @@ struct rh_handle {
   double* cf64[3];
   StateBuf B;
   double* locA[4];
-  double *part, *redout;
+  double* part;
   // levels
   LevelK<float> L32[kMaxLevels];
   LevelK<double> L64[kMaxLevels];
   double *cA, *cInv;
   float* cInv32;
   double* cInv64;
-  double* hred;  // pinned host copy of the reductions
+  double* hred;      // pinned host memory the reductions' second pass writes
+  double* hred_dev;  // its device address
   hipEvent_t ev0, ev1;
   // optional per-launch timing (event pairs on the handle's stream)
   static constexpr int kPool = 2048;
@@ -317,7 +318,6 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
   for (int q = 0; q < 4; ++q) h->B.loc[q] = cv.take<double>(N);
   for (int q = 0; q < 4; ++q) h->locA[q] = cv.take<double>(N);
   h->part = cv.take<double>((size_t)RS_COUNT * kPartCap + RS_COUNT);
-  h->redout = cv.take<double>(RS_COUNT);
   const bool mixed = p.precision == RH_PREC_MIXED;
   for (int l = 0; l < pl.nlev; ++l) {
     const int* d = pl.dims[l];
@@ -440,11 +440,10 @@ struct Timed {
 rh_status sync_reductions(rh_handle* h, unsigned mask) {
   {
     Timed tm(h, KK_FINALIZE);
-    launch_finalize(h->stream, h->part, h->redout, mask);
+    launch_finalize(h->stream, h->part, h->hred_dev, mask);
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(h->hred, h->redout, sizeof(double) * RS_COUNT, hipMemcpyDeviceToHost,
-                        h->stream));
+  // the results are in host memory once the stream has drained
   HIPCHK(hipStreamSynchronize(h->stream));
   if (h->timing) flush_timing(h);
   return RH_OK;
@@ -916,6 +915,8 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
   layout(h, *p, h->plan, base);
   hipError_t e1 = hipGetDevice(&h->device);
   hipError_t e2 = hipHostMalloc(reinterpret_cast<void**>(&h->hred), sizeof(double) * RS_COUNT);
+  if (e2 == hipSuccess)
+    e2 = hipHostGetDevicePointer(reinterpret_cast<void**>(&h->hred_dev), h->hred, 0);
   hipError_t e3 = hipEventCreate(&h->ev0);
   hipError_t e4 = hipEventCreate(&h->ev1);
   // no reducing kernel has run yet: every slot's block count is 0
@@ -924,7 +925,8 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
       e5 != hipSuccess) {
     const hipError_t es[5] = {e1, e2, e3, e4, e5};
-    const char* what[5] = {"hipGetDevice", "hipHostMalloc", "hipEventCreate", "hipEventCreate",
+    const char* what[5] = {"hipGetDevice", "hipHostMalloc / hipHostGetDevicePointer",
+                           "hipEventCreate", "hipEventCreate",
                            "hipMemsetAsync (reduction counts)"};
     int i = 0;
     while (es[i] == hipSuccess) ++i;
