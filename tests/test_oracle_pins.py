@@ -207,6 +207,51 @@ def test_fourier_mode_decay_one_step():
     np.testing.assert_allclose(n1, n0, rtol=1e-15)
 
 
+def test_fourier_mode_decay_theta_half_expanding():
+    """Transparent medium in an Einstein-de Sitter background, theta = 1/2:
+    D = c/R_min is uniform, and the two time levels of the
+    comoving diffusion and Hubble terms give a Fourier mode the closed-form
+    amplification
+      g_k = (1 - dt/2 (lam_n + H_n)) / (1 + dt/2 (lam_1 + H_1)),
+      lam_m = D / (a_m^2 h^2) 4 sum_d sin^2(pi k_d / N_d),
+    and the mean g_0 (lam = 0): each level takes its own a_m and H_m.  R_min
+    is set large enough that D = c/R_min and lam dt ~ 1 over a step of 5% of
+    the cosmic time (a_1/a_n - 1 = 3%)."""
+    dims = (12, 12, 12)
+    w = W.get(0)
+    w.dims = dims
+    w.bc = (W.BC_PERIODIC,) * 6
+    w.sigma0 = 0.0
+    w.alphaB_const = 0.0
+    w.theta = 0.5
+    w.cosmology = W.COSMO_EDS
+    w.hubble_h, w.Omega_m, w.Omega_L = 0.5, 1.0, 0.0
+    t0 = M.params_from_workload(w).cosmo.time_of_z(10.0)
+    dt = 0.05 * t0
+    a_n = M.params_from_workload(w).cosmo.a(t0)
+    h = w.box_comoving_cm / dims[0]
+    s = 4.0 * math.sin(math.pi / dims[0]) ** 2
+    R_min = C_LIGHT * s * dt / (a_n * h) ** 2  # lam_n dt = 1
+    p = M.params_from_workload(w, R_min=R_min)
+    nH = np.full(dims, 1e-3)
+    I = np.arange(dims[0])[:, None, None] * np.ones(dims)
+    k = (1, 0, 0)
+    E0 = 1e-20 * (1.0 + 0.01 * np.cos(2 * np.pi * k[0] * I / dims[0]))
+    e0 = np.full(dims, 1e12)
+    n0 = 0.5 * nH
+    E1, e1, n1 = N.step(p, t0, dt, nH, np.zeros(dims), E0, e0, n0, tol=1e-14)
+    a_n, a_1 = p.cosmo.a(t0), p.cosmo.a(t0 + dt)
+    H_n, H_1 = p.cosmo.hubble(t0), p.cosmo.hubble(t0 + dt)
+    D = C_LIGHT / R_min
+    lam_n, lam_1 = D * s / (a_n * p.h) ** 2, D * s / (a_1 * p.h) ** 2
+    g0 = (1.0 - 0.5 * dt * H_n) / (1.0 + 0.5 * dt * H_1)
+    gk = (1.0 - 0.5 * dt * (lam_n + H_n)) / (1.0 + 0.5 * dt * (lam_1 + H_1))
+    assert abs(gk) < 0.95 and abs(lam_1 / lam_n - 1.0) > 0.05
+    got = (E1 - E1.mean()) / (E0 - E0.mean())
+    np.testing.assert_allclose(got[:, 0, 0][[0, 2, 4, 6]], gk, rtol=1e-9)
+    assert E1.mean() == pytest.approx(g0 * E0.mean(), rel=1e-12)
+
+
 def _uniform_cell_workload(spectrum, isothermal, cosmo):
     w = W.get(1)
     w.dims = (2, 2, 2)
@@ -301,6 +346,56 @@ def test_local_terms_converge_to_ode_system(case):
     assert errs[2] < 0.05
 
 
+@pytest.mark.parametrize("case", ["iso_static_mono", "bb_eds_cooling"])
+def test_theta_half_is_second_order(case):
+    """theta = 1/2 (trapezoidal in both the radiation residual and the local
+    solutions): the explicit level enters with weight 1/2, and the step
+    converges to the ODE system at second order (error ratio 4 per halving
+    in every component).  A wrong time level in any explicit term (rates or
+    opacity taken at U instead of U^n, a_{n+1} or H_{n+1} instead of a_n,
+    H_n) drops some component to first order.  Regimes are chosen non-stiff
+    (rate x step < 1) so the trapezoidal rule is in its asymptotic range;
+    the expanding case spans a Hubble time of about 0.6."""
+    if case == "iso_static_mono":
+        w = _uniform_cell_workload(W.SPEC_MONO, True, W.COSMO_STATIC)
+        nHv, srcv, T_span = 1e-6, 4e-30, 5e12
+    else:
+        w = _uniform_cell_workload(W.SPEC_BLACKBODY, False, W.COSMO_EDS)
+        nHv, srcv, T_span = 1.7e-13, 1e-39, 1e16
+    w.theta = 0.5
+    p = M.params_from_workload(w)
+    dims = w.dims
+    nH = np.full(dims, nHv)
+    src = np.full(dims, srcv)
+    t0 = 0.0 if p.cosmo.kind == 0 else p.cosmo.time_of_z(10.0)
+    E0, e0, n0 = M.initial_state(p, nH, 1.2e-3, 100.0, 1e-35)
+    f = _ode_rhs(p, nHv, srcv, None)
+    scale = np.array([srcv * T_span, nHv, e0.flat[0]])
+
+    def g(tau, y):
+        return np.array(f(t0 + tau * T_span, y * scale)) * T_span / scale
+    y0 = np.array([E0.flat[0], n0.flat[0], e0.flat[0]]) / scale
+    sol = integrate.solve_ivp(g, (0.0, 1.0), y0, method="Radau", rtol=1e-13, atol=1e-15)
+    assert sol.status == 0, sol.message
+    ref = sol.y[:, -1] * scale
+    errs = []
+    for nsteps in (8, 16, 32):
+        dt = T_span / nsteps
+        E, e, n = E0, e0, n0
+        t = t0
+        for _ in range(nsteps):
+            E, e, n = N.step(p, t, dt, nH, src, E, e, n, tol=1e-14)
+            t += dt
+        err = [abs(E.flat[0] - ref[0]) / abs(ref[0]), abs(n.flat[0] - ref[1]) / nHv]
+        if not p.isothermal:
+            err.append(abs(e.flat[0] - ref[2]) / abs(ref[2]))
+        errs.append(err)
+    errs = np.array(errs)
+    ratios = errs[:-1] / errs[1:]
+    np.testing.assert_allclose(ratios, 4.0, rtol=0.02)
+    assert np.all(errs[-1] < 1e-3)
+
+
 def test_photon_number_conservation_mono():
     """Monochromatic isothermal run without recombination or expansion:
     every absorbed photon ionises one atom, so the radiation energy gained
@@ -332,6 +427,29 @@ def test_photon_energy_budget_telescopes(cfg, dims):
         ctx = M.make_context(p, t0 + s * dt, dt, nH, src, E, e, n)
         E, e, n = N.step(p, t0 + s * dt, dt, nH, src, E, e, n, tol=1e-13)
         assert diagnostics.photon_budget_defect(p, ctx, E, n) < 1e-10
+        assert np.all(n >= 0) and np.all(n <= nH)
+
+
+@pytest.mark.parametrize("cfg,dims,theta", [(0, (8, 8, 8), 0.51), (2, (10, 12, 8), 0.6),
+                                            (1, (8, 8, 8), 0.51)])
+def test_photon_energy_budget_theta_lt1(cfg, dims, theta):
+    """The budget with both time levels (explicit weight 1 - theta): zero-flux
+    walls (Stromgren, EdS sphere) and periodic walls (lognormal); short steps
+    keep the explicit half admissible."""
+    w = W.scaled(cfg, dims)
+    w.theta = theta
+    p = M.params_from_workload(w)
+    nH = W.density_field(w)
+    src = M.source_field(p, W.photon_rate_field(w))
+    E, e, n = M.initial_state(p, nH, w.x0, w.T0, w.E0)
+    t0, dt, _ = M.schedule(p, w)
+    dt = dt * 0.02
+    for s in range(3):
+        ctx = M.make_context(p, t0 + s * dt, dt, nH, src, E, e, n)
+        E, e, n = N.step(p, t0 + s * dt, dt, nH, src, E, e, n, tol=1e-13)
+        assert diagnostics.photon_budget_defect(p, ctx, E, n) < 1e-10
+        # the theta = 1 budget does not hold for this step (the explicit level matters)
+        assert diagnostics.photon_budget_defect(p.with_(theta=1.0), ctx, E, n) > 1e-6
         assert np.all(n >= 0) and np.all(n <= nH)
 
 
@@ -494,3 +612,36 @@ def test_sg_tau_is_recombination_integral():
         val, _ = integrate.quad(lambda b: b ** -2.5, 1.0, a)
         assert analytic.sg_tau(a, lam, q0, z0) == pytest.approx(lam * val / math.sqrt(1 + z0),
                                                                 rel=1e-12)
+
+
+def test_sg_tau_open_is_recombination_integral():
+    """q0 = 0.05 (open universe, Omega_m = 0.1, h = 1): tau(a) equals the
+    recombination integral alpha n_H0 int (a0/a(t))^3 dt along the open
+    expansion law a(t) of the cosmology module, with
+    lambda = alpha n_H0 / (H0 (1 + z0))."""
+    q0, z0 = 0.05, 4.0
+    cos = cosmology.Cosmology(cosmology.OPEN, 1.0, 2.0 * q0, 0.0)
+    a0 = 1.0 / (1.0 + z0)
+    t0 = cos.time_of_a(a0)
+    alpha_nH0 = 1e-17  # s^-1; only the product enters
+    lam = alpha_nH0 / (cos.H0 * (1.0 + z0))
+    for abar in (1.5, 3.0, 5.0):
+        t1 = cos.time_of_a(abar * a0)
+        val, _ = integrate.quad(lambda t: (a0 / cos.a(t)) ** 3, t0, t1, epsabs=0.0,
+                                epsrel=1e-12, limit=200)
+        assert analytic.sg_tau(abar, lam, q0, z0) == pytest.approx(alpha_nH0 * val, rel=1e-9)
+
+
+def test_sg_front_photon_counting_limit_open():
+    """q0 = 0.05, lambda -> 0: r_I^3 / r_S0^3 = alpha n_H0 (t - t0) (every photon
+    ionises one atom; r_S0^3 = 3 Q / (4 pi alpha n_H0^2)), with t(a) from the
+    open expansion law."""
+    q0, z0 = 0.05, 4.0
+    cos = cosmology.Cosmology(cosmology.OPEN, 1.0, 2.0 * q0, 0.0)
+    a0 = 1.0 / (1.0 + z0)
+    t0 = cos.time_of_a(a0)
+    lam = 1e-9
+    for abar in (1.2, 2.0, 5.0):
+        dt = cos.time_of_a(abar * a0) - t0
+        exact = lam * cos.H0 * (1.0 + z0) * dt
+        assert analytic.sg_front(abar, lam, q0, z0) ** 3 == pytest.approx(exact, rel=1e-6)
