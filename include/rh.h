@@ -93,7 +93,13 @@ typedef struct rh_params {
   int32_t newton_max_it;       /* Newton iterations before RH_ENEWTON                    */
   int32_t ls_max_cuts;         /* line-search halvings per iteration                     */
   double lin_forcing;          /* linear solve to ||r|| <= lin_forcing ||f(U_k)|| (1e-13) */
-  int32_t lin_max_it;          /* outer (defect-correction) iterations per Newton step   */
+  int32_t lin_max_it;          /* outer linear iterations (V-cycles) per solve (500).     */
+                               /* rh_implicit_step: a solve that stops here without      */
+                               /* reaching its forcing is used as an inexact Newton      */
+                               /* direction (Newton still stops only at newton_tol) and  */
+                               /* is counted in rh_step_stats.lin_cap_hits.              */
+                               /* rh_adjoint_step: returns RH_ELINEAR instead (nothing   */
+                               /* corrects an inexact transpose solve).                  */
   int32_t mg_pre, mg_post;     /* red-black Gauss-Seidel sweeps before / after coarsening */
   int32_t mg_coarse_max;       /* stop coarsening at <= this many cells (<= 512)         */
   int32_t krylov;              /* outer linear iteration: 1 = conjugate gradients with   */
@@ -118,9 +124,22 @@ typedef struct rh_step_stats {
   int32_t ls_cuts;             /* line-search halvings                                   */
   int32_t local_its_max;       /* most per-cell local Newton iterations in any call      */
   double res0, res_final;      /* ||f|| at the start and at the end                      */
-  double lin_res_max;          /* largest final relative linear residual                 */
-  double t_ms[8];              /* GPU time per phase: 0 total, 1 setup, 2 local+residual, */
-                               /* 3 coarse setup, 4 V-cycles, 5 defect/accumulate        */
+  double lin_res_max;          /* largest final linear residual of a Newton iteration,   */
+                               /* relative to that iteration's ||f|| (E-weighted norm);  */
+                               /* the forcing is met when <= lin_forcing                 */
+  double t_ms[8];              /* GPU time (ms) from events on the handle's stream:      */
+                               /* [0] the whole call; [1..5] partition it by phase:      */
+                               /* 1 state copies, face limiter, coarse face hierarchy;   */
+                               /* 2 local solves, residuals and norms (Newton iterates   */
+                               /* and line-search trials; the adjoint's local terms);    */
+                               /* 3 coarse-level operators and the coarsest inverse;     */
+                               /* 4 V-cycles; 5 the outer linear iteration (conjugate-   */
+                               /* gradient or defect-correction kernels and their        */
+                               /* reductions).  Host latency between launches counts in  */
+                               /* the phase it interrupts.  [6], [7] are 0.              */
+  int32_t lin_cap_hits;        /* linear solves that stopped without reaching their      */
+                               /* target (at lin_max_it, on stagnation or breakdown)     */
+  int32_t lin_its_max;         /* most V-cycles in one linear solve of the call          */
 } rh_step_stats;
 
 /* Statistics of rh_advance (host memory). */
@@ -173,7 +192,10 @@ rh_status rh_implicit_step(rh_handle* h, double t_n_s, double dt_s, const double
  * Newton system; after local elimination the same symmetric Schur operator
  * as the forward step) and return lambda^n = -(df/dU^n)^T mu in (lE, le,
  * lnHI) (overwritten), and accumulate g_src += -(df/dsrc)^T mu and
- * g_nH += -(df/dnH)^T mu.  E_n..nHI_n and E_1..nHI_1 are the checkpoints
+ * g_nH += -(df/dnH)^T mu.  The transposed solve runs to ||r||_2 <= 1e-13 of
+ * its right-hand side; if it stops short (lin_max_it reached, stagnation)
+ * the call returns RH_ELINEAR and leaves lE, le, lnHI, g_src, g_nH as they
+ * were.  E_n..nHI_n and E_1..nHI_1 are the checkpoints
  * U^n and U^{n+1} (read only).  le and the e-checkpoints are ignored for
  * isothermal runs.  stats may be NULL. */
 rh_status rh_adjoint_step(rh_handle* h, double t_n_s, double dt_s, const double* nH,
@@ -271,6 +293,28 @@ rh_status rh_schur_solve(rh_handle* h, double t_n_s, double dt_s, const double* 
                          const double* nHI_n, const double* E, const double* e,
                          const double* nHI, const double* b, double* x, double rel_tol,
                          int32_t max_it, int32_t* iters, double* rel_res);
+
+/* Initial fields of a run (verification and reionisation sections start
+ * from uniform radiation, a given ionised fraction and a given temperature):
+ * E = E0 everywhere, nHI = (1 - x0) nH and, when e is not NULL, the specific
+ * gas energy of temperature T0_K at ionised fraction x0 from the ideal-gas
+ * relation T = (gamma - 1) mu m_H e / k_B with mu = 1 / (1 + x0) (pure
+ * hydrogen; the printed temperature and equation-of-state equations compose
+ * to an extra factor gamma - 1, which is not used).  Isothermal runs use
+ * T_iso_K instead of T0_K and accept e == NULL; otherwise e is required.
+ * nH: device, read only (every entry finite and > 0, else RH_ENONFINITE,
+ * outputs then partly written).  0 <= x0 < 1, T0_K > 0, finite E0 >= 0,
+ * else RH_EINVAL.  Synchronises the stream. */
+rh_status rh_initial_state(rh_handle* h, const double* nH, double x0, double T0_K, double E0,
+                           double* E, double* e, double* nHI);
+
+/* Emissivity src = 4 pi eta (erg cm^-3 s^-1, comoving) of point sources
+ * from their photon rates: photon_rate[P] (photons s^-1 emitted in cell P;
+ * the sum of the sources in that cell) times the mean photon energy of the
+ * spectrum (equation grey_definition) over the comoving cell volume h^3.
+ * Device arrays; RH_ENONFINITE if a rate is negative or not finite (src
+ * then written anyway).  Synchronises the stream. */
+rh_status rh_source_field(rh_handle* h, const double* photon_rate, double* src);
 
 /* Derived constants of the handle: out[0] sigma_E (cm^2), out[1] K_Gamma
  * (cm^2 erg^-1), out[2] K_G (cm^2), out[3] eps_bar (erg, mean photon energy),

@@ -55,6 +55,7 @@ class RhStepStats(ctypes.Structure):
         ("local_its_max", _i32),
         ("res0", _f64), ("res_final", _f64), ("lin_res_max", _f64),
         ("t_ms", _f64 * 8),
+        ("lin_cap_hits", _i32), ("lin_its_max", _i32),
     ]
 
     def as_dict(self):
@@ -101,6 +102,8 @@ SIGNATURES = {
                               _vp, _vp, _f64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]),
     "rh_schur_operator": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                  _vp, _vp, _vp, _vp]),
+    "rh_initial_state": (_i32, [_vp, _vp, _f64, _f64, _f64, _vp, _vp, _vp]),
+    "rh_source_field": (_i32, [_vp, _vp, _vp]),
     "rh_get_constants": (_i32, [_vp, ctypes.POINTER(_f64), _i32]),
     "rh_cosmology_at": (_i32, [_PP, _f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "rh_cosmic_time": (_i32, [_PP, _f64, ctypes.POINTER(_f64)]),

@@ -283,8 +283,18 @@ struct rh_handle {
   double kms[KK_COUNT] = {};
   long long kcount[KK_COUNT] = {};
   std::string err;
+  // per-phase GPU time of a step: an event is recorded on the stream where
+  // the step enters another phase; after each stream synchronisation the
+  // completed intervals are folded into pms[phase] (contiguous intervals, so
+  // the phases partition the step's GPU time)
+  static constexpr int kPhaseEv = 64;
+  hipEvent_t pev[kPhaseEv];
+  int pph[kPhaseEv];
+  int npev = 0, cur_phase = -1;
+  bool phases_on = false, phase_events = false;
+  double pms[8] = {};
   // statistics of the current call
-  int lin_its, local_its_max;
+  int lin_its, local_its_max, lin_cap_hits, lin_its_max;
   double last_E_s = 1.0;  // E_s of the last step set up (weight of E in the norms)
   // conjugate-gradient dot products requested from the V-cycle's last sweep
   SweepDots dots{};
@@ -437,6 +447,53 @@ struct Timed {
   }
 };
 
+// Phases of a step (rh_step_stats.t_ms[1..5]).
+enum Phase { PH_SETUP = 1, PH_EVAL = 2, PH_COARSE = 3, PH_VCYCLE = 4, PH_OUTER = 5 };
+
+void phase_begin(rh_handle* h) {
+  h->npev = 0;
+  h->cur_phase = -1;
+  for (double& v : h->pms) v = 0.0;
+  h->phases_on = h->phase_events;
+}
+
+void phase_mark(rh_handle* h, int phase) {
+  if (!h->phases_on || h->cur_phase == phase || h->npev == rh_handle::kPhaseEv) return;
+  if (hipEventRecord(h->pev[h->npev], h->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  h->pph[h->npev++] = phase;
+  h->cur_phase = phase;
+}
+
+// After a stream synchronisation: fold the completed intervals; the last
+// marker stays open.
+void phase_fold(rh_handle* h) {
+  if (!h->phases_on || h->npev < 2) return;
+  for (int i = 0; i + 1 < h->npev; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->pev[i], h->pev[i + 1]) == hipSuccess) h->pms[h->pph[i]] += ms;
+  }
+  std::swap(h->pev[0], h->pev[h->npev - 1]);
+  h->pph[0] = h->pph[h->npev - 1];
+  h->npev = 1;
+  (void)hipGetLastError();
+}
+
+// After `end` has completed: close the open interval at `end`.
+void phase_close(rh_handle* h, hipEvent_t end) {
+  phase_fold(h);
+  if (h->phases_on && h->npev == 1) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->pev[0], end) == hipSuccess) h->pms[h->pph[0]] += ms;
+    (void)hipGetLastError();
+  }
+  h->npev = 0;
+  h->cur_phase = -1;
+  h->phases_on = false;
+}
+
 rh_status sync_reductions(rh_handle* h, unsigned mask) {
   {
     Timed tm(h, KK_FINALIZE);
@@ -446,6 +503,7 @@ rh_status sync_reductions(rh_handle* h, unsigned mask) {
   // the results are in host memory once the stream has drained
   HIPCHK(hipStreamSynchronize(h->stream));
   if (h->timing) flush_timing(h);
+  phase_fold(h);
   return RH_OK;
 }
 
@@ -454,6 +512,7 @@ double nvars(const rh_handle* h) { return h->p.isothermal ? 2.0 : 3.0; }
 // Per-step setup: U^n copies are already in En/en/nn.
 rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
   const bool mixed = h->p.precision == RH_PREC_MIXED;
+  phase_mark(h, PH_SETUP);
   float* c32[3] = {nullptr, nullptr, nullptr};
   if (mixed)
     for (int a = 0; a < 3; ++a) c32[a] = h->L32[0].cf[a];
@@ -492,6 +551,7 @@ struct EvalOut {
 rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const double* dE,
                      double lam, const StateBuf& out, bool predictor, const double* nH, int mode,
                      double* fE_out, double* fe_out, double* fn_out, EvalOut& res) {
+  phase_mark(h, PH_EVAL);
   LocalArgs a{};
   a.Ek = cur.E; a.dE = dE; a.lam = lam;
   a.ek = cur.e; a.nk = cur.n;
@@ -555,6 +615,7 @@ double* coarse_inverse<double>(rh_handle* h) { return h->cInv64; }
 template <class T>
 rh_status coarse_setup(rh_handle* h) {
   LevelK<T>* L = levels<T>(h);
+  phase_mark(h, PH_COARSE);
   {
     Timed tm(h, KK_COARSE);
     for (int l = 1; l < h->plan.nlev; ++l) launch_coarse_diag<T>(h->stream, L[l - 1], L[l]);
@@ -635,13 +696,14 @@ void vcycle(rh_handle* h, int l) {
 template <class T>
 rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
                        double target_2, int max_it, double** dE_final, int* its_out,
-                       double* w_out, double* l2_out) {
+                       double* w_out, double* l2_out, bool* reached) {
   LevelK<T>* L = levels<T>(h);
   rh_status st = coarse_setup<T>(h);
   if (st != RH_OK) return st;
   double* dE_in = h->dEa;
   double* dE_out = h->dEb;
   *its_out = 0;
+  *reached = true;
   if (rmax0 == 0.0) {
     HIPCHK(hipMemsetAsync(dE_in, 0, sizeof(double) * h->N, h->stream));
     *dE_final = dE_in;
@@ -650,6 +712,7 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
     return RH_OK;
   }
   double sigma_b = rmax0, rmax_cur = rmax0;
+  phase_mark(h, PH_OUTER);
   launch_cast_scale<T>(h->stream, h->N, h->rS, 1.0 / sigma_b, L[0].b);
   HIPCHK(hipGetLastError());
   bool first = true;
@@ -657,7 +720,9 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
   int slow = 0;
   double w = INFINITY, l2 = INFINITY;
   for (int j = 1; j <= max_it; ++j) {
+    phase_mark(h, PH_VCYCLE);
     vcycle<T>(h, 0);
+    phase_mark(h, PH_OUTER);
     DefectArgs a{};
     a.rS = h->rS; a.dE_in = dE_in; a.dE_out = dE_out;
     a.diag64 = h->diag64;
@@ -686,6 +751,7 @@ rh_status linear_solve(rh_handle* h, const StepK& k, double rmax0, double target
     if (slow >= 3) break;  // stagnated at the rounding floor
     prev = w;
   }
+  *reached = w <= target_w || l2 <= target_2 || rmax_cur == 0.0;
   *dE_final = dE_in;
   *w_out = w;
   *l2_out = l2;
@@ -703,7 +769,9 @@ void precondition(rh_handle* h, const StepK& k, double sigma, const double* q) {
   h->dots = SweepDots{sigma, h->r64, q, h->part};
   h->dots_wanted = true;
   h->dots_done = false;
+  phase_mark(h, PH_VCYCLE);
   vcycle<T>(h, 0);
+  phase_mark(h, PH_OUTER);
   h->dots_wanted = false;
   if (!h->dots_done) {
     Timed tm(h, KK_PCG_PRE);
@@ -713,19 +781,22 @@ void precondition(rh_handle* h, const StepK& k, double sigma, const double* q) {
 
 template <class T>
 rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w, double target_2,
-                    int max_it, double** x_final, int* its_out, double* w_out, double* l2_out) {
+                    int max_it, double** x_final, int* its_out, double* w_out, double* l2_out,
+                    bool* reached) {
   LevelK<T>* L = levels<T>(h);
   rh_status st = coarse_setup<T>(h);
   if (st != RH_OK) return st;
   double* x = h->dEa;
   *its_out = 0;
   *x_final = x;
+  *reached = true;
   if (rmax0 == 0.0) {
     HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * h->N, h->stream));
     *w_out = 0.0;
     *l2_out = 0.0;
     return RH_OK;
   }
+  phase_mark(h, PH_OUTER);
   HIPCHK(hipMemcpyAsync(h->r64, h->rS, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
   double sigma_b = rmax0;
   {
@@ -794,22 +865,27 @@ rh_status pcg_solve(rh_handle* h, const StepK& k, double rmax0, double target_w,
     launch_xaxpy(h->stream, h->N, alpha_prev, p_last, x, *its_out == 1);
     HIPCHK(hipGetLastError());
   }
+  *reached = w <= target_w || l2 <= target_2 || rmax_cur == 0.0;
   *w_out = w;
   *l2_out = l2;
   return RH_OK;
 }
 
+// Linear solve of the Schur system; *reached reports whether the stopping
+// test was met (false: stopped at max_it, on stagnation or on a CG breakdown
+// after the first iteration).
 rh_status solve_linear(rh_handle* h, const StepK& k, double rmax0, double target_w,
                        double target_2, int max_it, double** dE_final, int* its, double* w,
-                       double* l2) {
+                       double* l2, bool* reached) {
   const bool mixed = h->p.precision == RH_PREC_MIXED;
   if (h->p.krylov) {
-    if (mixed) return pcg_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
-    return pcg_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+    if (mixed)
+      return pcg_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2, reached);
+    return pcg_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2, reached);
   }
   if (mixed)
-    return linear_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
-  return linear_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2);
+    return linear_solve<float>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2, reached);
+  return linear_solve<double>(h, k, rmax0, target_w, target_2, max_it, dE_final, its, w, l2, reached);
 }
 
 rh_status check_ptrs(rh_handle* h, std::initializer_list<const void*> ptrs) {
@@ -863,7 +939,7 @@ void rh_default_params(rh_params* p) {
   p->newton_max_it = 30;
   p->ls_max_cuts = 10;
   p->lin_forcing = 1.0e-13;
-  p->lin_max_it = 60;
+  p->lin_max_it = 500;
   p->precision = RH_PREC_FP64;
   p->mg_pre = 2;
   p->mg_post = 2;
@@ -919,6 +995,13 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
     e2 = hipHostGetDevicePointer(reinterpret_cast<void**>(&h->hred_dev), h->hred, 0);
   hipError_t e3 = hipEventCreate(&h->ev0);
   hipError_t e4 = hipEventCreate(&h->ev1);
+  int made = 0;
+  while (made < rh_handle::kPhaseEv && e3 == hipSuccess &&
+         (e3 = hipEventCreate(&h->pev[made])) == hipSuccess)
+    ++made;
+  h->phase_events = made == rh_handle::kPhaseEv;
+  if (!h->phase_events)
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(h->pev[i]);
   // no reducing kernel has run yet: every slot's block count is 0
   hipError_t e5 = hipMemsetAsync(h->part + (size_t)RS_COUNT * kPartCap, 0,
                                  sizeof(double) * RS_COUNT, h->stream);
@@ -953,7 +1036,11 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
   h->lin_its = 0;
   h->local_its_max = 0;
   h->lin_res_max = 0.0;
+  h->lin_cap_hits = 0;
+  h->lin_its_max = 0;
   HIPCHK(hipEventRecord(h->ev0, h->stream));
+  phase_begin(h);
+  phase_mark(h, PH_SETUP);
   StepK k = make_step(h, t_n, dt);
   if ((st = copy_state(h, h->En, h->en, h->nn, E, e, nHI)) != RH_OK) return st;
   if ((st = setup_step(h, k, src)) != RH_OK) return st;
@@ -986,10 +1073,13 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     double* dE = nullptr;
     int its = 0;
     double w = 0, l2 = 0;
+    bool reached = true;
     st = solve_linear(h, k, ev.rmax, h->p.lin_forcing * ev.norm, 0.0, h->p.lin_max_it, &dE, &its,
-                      &w, &l2);
+                      &w, &l2, &reached);
     if (st != RH_OK) { result = st; break; }
     h->lin_its += its;
+    h->lin_its_max = std::max(h->lin_its_max, its);
+    if (!reached) ++h->lin_cap_hits;
     if (ev.norm > 0) h->lin_res_max = std::max(h->lin_res_max, w / ev.norm);
     ++newton_its;
     const double f0 = ev.norm;
@@ -1011,6 +1101,7 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     }
     std::swap(cur, oth);
   }
+  phase_mark(h, PH_SETUP);
   if (result == RH_OK) {
     if (cur->E != E) {
       if ((st = copy_state(h, E, e, nHI, cur->E, cur->e, cur->n)) != RH_OK) return st;
@@ -1020,6 +1111,7 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
   }
   HIPCHK(hipEventRecord(h->ev1, h->stream));
   HIPCHK(hipEventSynchronize(h->ev1));
+  phase_close(h, h->ev1);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->newton_its = newton_its;
@@ -1032,6 +1124,9 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     float ms = 0;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     stats->t_ms[0] = ms;
+    for (int q = 1; q <= 5; ++q) stats->t_ms[q] = h->pms[q];
+    stats->lin_cap_hits = h->lin_cap_hits;
+    stats->lin_its_max = h->lin_its_max;
   }
   return result;
 }
@@ -1273,7 +1368,8 @@ rh_status rh_schur_solve(rh_handle* h, double t_n, double dt, const double* nH, 
   double* dE = nullptr;
   int its = 0;
   double w = 0, l2 = 0;
-  st = solve_linear(h, k, bmax, 0.0, rel_tol * bnorm, max_it, &dE, &its, &w, &l2);
+  bool reached = true;
+  st = solve_linear(h, k, bmax, 0.0, rel_tol * bnorm, max_it, &dE, &its, &w, &l2, &reached);
   if (st != RH_OK) return st;
   HIPCHK(hipMemcpyAsync(x, dE, sizeof(double) * h->N, hipMemcpyDeviceToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -1299,6 +1395,8 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   h->lin_its = 0;
   h->local_its_max = 0;
   HIPCHK(hipEventRecord(h->ev0, h->stream));
+  phase_begin(h);
+  phase_mark(h, PH_SETUP);
   StepK k = make_step(h, t_n, dt);
   // recompute the step's face limiter from U^n and the local terms and the
   // Schur operator at the converged U^{n+1}
@@ -1311,6 +1409,7 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   if (st != RH_OK) return st;
   if (!ev.finite) return fail(h, RH_ENONFINITE, "non-finite state in the adjoint step");
   // S mu_E = lE - (B^-1 C)^T lambda_loc
+  phase_mark(h, PH_OUTER);
   launch_adj_rhs(h->stream, k, lE, le, lnHI, h->locA[0], h->locA[1], h->rS, h->part);
   HIPCHK(hipGetLastError());
   if ((st = sync_reductions(h, kAllSlots)) != RH_OK) return st;
@@ -1320,9 +1419,33 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   double* mu = nullptr;
   int its = 0;
   double w = 0, l2 = 0;
-  st = solve_linear(h, k, rmax, 0.0, 1e-13 * rnorm, h->p.lin_max_it, &mu, &its, &w, &l2);
+  bool reached = true;
+  st = solve_linear(h, k, rmax, 0.0, 1e-13 * rnorm, h->p.lin_max_it, &mu, &its, &w, &l2,
+                    &reached);
   if (st != RH_OK) return st;
   h->lin_its = its;
+  if (!reached) {
+    // no outer iteration corrects an inexact transpose solve: fail without
+    // touching lE, le, lnHI, g_src, g_nH
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->phases_on = false;
+    h->npev = 0;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->lin_its_total = its;
+      stats->lin_its_max = its;
+      stats->lin_cap_hits = 1;
+      stats->res0 = rnorm;
+      stats->res_final = l2;
+      stats->lin_res_max = rnorm > 0 ? l2 / rnorm : 0.0;
+    }
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "adjoint linear solve stopped after %d cycles at relative residual %.3e "
+                  "(target 1e-13; raise lin_max_it)", its, rnorm > 0 ? l2 / rnorm : 0.0);
+    return fail(h, RH_ELINEAR, buf);
+  }
+  phase_mark(h, PH_EVAL);
   AdjArgs a{};
   a.E1 = E_1; a.e1 = iso ? nullptr : e_1; a.n1 = nHI_1;
   a.En = h->En; a.en = h->en; a.nn = h->nn;
@@ -1335,16 +1458,54 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(h->ev1, h->stream));
   HIPCHK(hipEventSynchronize(h->ev1));
+  phase_close(h, h->ev1);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->lin_its_total = its;
+    stats->lin_its_max = its;
     stats->res0 = rnorm;
     stats->res_final = l2;
     stats->lin_res_max = rnorm > 0 ? l2 / rnorm : 0.0;
     float ms = 0;
     (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
     stats->t_ms[0] = ms;
+    for (int q = 1; q <= 5; ++q) stats->t_ms[q] = h->pms[q];
   }
+  return RH_OK;
+}
+
+rh_status rh_initial_state(rh_handle* h, const double* nH, double x0, double T0_K, double E0,
+                           double* E, double* e, double* nHI) {
+  if (!h) return RH_EINVAL;
+  const bool iso = h->p.isothermal != 0;
+  rh_status st = check_ptrs(h, {nH, E, nHI});
+  if (st != RH_OK) return st;
+  if (e && (st = check_ptrs(h, {e})) != RH_OK) return st;
+  if (!iso && !e) return fail(h, RH_EINVAL, "e is required unless the run is isothermal");
+  const double T = iso ? h->p.T_iso_K : T0_K;
+  if (!(x0 >= 0.0 && x0 < 1.0) || !(T > 0.0) || !std::isfinite(T) || !(E0 >= 0.0) ||
+      !std::isfinite(E0))
+    return fail(h, RH_EINVAL, "need 0 <= x0 < 1, T0 > 0 and finite E0 >= 0");
+  // ideal gas: T = (gamma - 1) mu m_H e / k_B, mu = 1 / (1 + x)
+  const double mu = 1.0 / (1.0 + x0);
+  const double e0 = kKB * T / ((h->p.gamma - 1.0) * mu * kMH);
+  launch_init_state(h->stream, h->N, E0, 1.0 - x0, e0, nH, E, e, nHI, h->part);
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, slot_bit(RS_NONFINITE))) != RH_OK) return st;
+  if (h->hred[RS_NONFINITE] != 0.0) return fail(h, RH_ENONFINITE, "n_H must be finite and > 0");
+  return RH_OK;
+}
+
+rh_status rh_source_field(rh_handle* h, const double* photon_rate, double* src) {
+  if (!h) return RH_EINVAL;
+  rh_status st = check_ptrs(h, {photon_rate, src});
+  if (st != RH_OK) return st;
+  const double scale = h->g.eps_bar / (h->h * h->h * h->h);
+  launch_scale_field(h->stream, h->N, scale, photon_rate, src, h->part);
+  HIPCHK(hipGetLastError());
+  if ((st = sync_reductions(h, slot_bit(RS_NONFINITE))) != RH_OK) return st;
+  if (h->hred[RS_NONFINITE] != 0.0)
+    return fail(h, RH_ENONFINITE, "photon rates must be finite and >= 0");
   return RH_OK;
 }
 
@@ -1439,6 +1600,8 @@ void rh_destroy(rh_handle* h) {
   if (h->hred) (void)hipHostFree(h->hred);
   (void)hipEventDestroy(h->ev0);
   (void)hipEventDestroy(h->ev1);
+  if (h->phase_events)
+    for (int i = 0; i < rh_handle::kPhaseEv; ++i) (void)hipEventDestroy(h->pev[i]);
   delete h;
 }
 

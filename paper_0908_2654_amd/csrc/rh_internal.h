@@ -94,6 +94,12 @@ constexpr unsigned slot_bit(int s) { return 1u << s; }
 void launch_change_norm(hipStream_t s, long long N, double E_s, const double* E, const double* e,
                         const double* n, const double* En, const double* en, const double* nn,
                         const double* nH, double* part);
+// E = E0, n = keep nH, e = e0 (e may be null); RS_NONFINITE flags a bad nH.
+void launch_init_state(hipStream_t s, long long N, double E0, double keep, double e0,
+                       const double* nH, double* E, double* e, double* n, double* part);
+// out = scale in; RS_NONFINITE flags a negative or non-finite input.
+void launch_scale_field(hipStream_t s, long long N, double scale, const double* in, double* out,
+                        double* part);
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
                        float* cf32_x, float* cf32_y, float* cf32_z, double* rhsn,

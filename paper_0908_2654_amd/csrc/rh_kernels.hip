@@ -648,6 +648,58 @@ void launch_change_norm(hipStream_t s, long long N, double E_s, const double* E,
                      en, nn, nH, part);
 }
 
+// Initial fields of a run: E = E0, n_HI = keep * n_H and, when e is given,
+// e = e0 (the host evaluates the gas energy of the initial temperature);
+// an input n_H that is not finite and positive raises the non-finite flag.
+__global__ void __launch_bounds__(kBlock)
+k_init_state(long long N, double E0, double keep, double e0, const double* __restrict__ nH,
+             double* __restrict__ E, double* __restrict__ e, double* __restrict__ n,
+             double* __restrict__ part) {
+  double bad = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    const double h = nH[idx];
+    if (!(h > 0.0) || !isfinite(h)) bad = 1.0;
+    E[idx] = E0;
+    n[idx] = keep * h;
+    if (e) e[idx] = e0;
+  }
+  double v[1] = {bad};
+  const int im[1] = {1};
+  const int sl[1] = {RS_NONFINITE};
+  block_reduce_store<1>(v, im, sl, part);
+}
+
+void launch_init_state(hipStream_t s, long long N, double E0, double keep, double e0,
+                       const double* nH, double* E, double* e, double* n, double* part) {
+  hipLaunchKernelGGL(k_init_state, dim3(red_grid(N)), dim3(kBlock), 0, s, N, E0, keep, e0, nH, E,
+                     e, n, part);
+}
+
+// out = scale * in (emissivity from photon rates: scale = mean photon energy
+// / cell volume); flags entries that are negative or not finite.
+__global__ void __launch_bounds__(kBlock)
+k_scale_field(long long N, double scale, const double* __restrict__ in, double* __restrict__ out,
+              double* __restrict__ part) {
+  double bad = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+       idx += (long long)blockDim.x * gridDim.x) {
+    const double q = in[idx];
+    if (!(q >= 0.0) || !isfinite(q)) bad = 1.0;
+    out[idx] = q * scale;
+  }
+  double v[1] = {bad};
+  const int im[1] = {1};
+  const int sl[1] = {RS_NONFINITE};
+  block_reduce_store<1>(v, im, sl, part);
+}
+
+void launch_scale_field(hipStream_t s, long long N, double scale, const double* in, double* out,
+                        double* part) {
+  hipLaunchKernelGGL(k_scale_field, dim3(red_grid(N)), dim3(kBlock), 0, s, N, scale, in, out,
+                     part);
+}
+
 void launch_finalize(hipStream_t s, const double* part, double* out, unsigned mask) {
   hipLaunchKernelGGL(k_finalize, dim3(RS_COUNT), dim3(kBlock), 0, s, part, out, mask);
 }

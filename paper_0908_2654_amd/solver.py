@@ -138,6 +138,17 @@ class Solver:
         keys = ["sigma_E", "K_Gamma", "K_G", "eps_bar", "hnu0", "h", "levels", "coarse_cells"]
         return dict(zip(keys, list(out)))
 
+    def initial_state(self, nH, x0, T0, E0, E, e, nHI):
+        """Fill (E, e, nHI) in place: uniform E0, ionised fraction x0 and the gas
+        energy of temperature T0 (e may be None for isothermal runs)."""
+        s = lib.rh_initial_state(self._h, _ptr(nH), float(x0), float(T0), float(E0), _ptr(E),
+                                 _ptr(e), _ptr(nHI))
+        check(s, self._h)
+
+    def source_field(self, photon_rate, src):
+        """src = 4 pi eta from photons/s per cell (in place into src)."""
+        check(lib.rh_source_field(self._h, _ptr(photon_rate), _ptr(src)), self._h)
+
     def step(self, t, dt, nH, src, E, e, nHI) -> dict:
         """One implicit step in place on (E, e, nHI); returns the step statistics."""
         st = RhStepStats()

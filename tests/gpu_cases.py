@@ -19,10 +19,16 @@ CASES = {
     # FP64, nx >= 4)
     "lognormal_tall": (2, (8, 16, 64), {"n_sources": 6}),
     "stromgren_tall": (0, (8, 16, 64), {}),
+    # several x chunks and ragged (y, z) tiles: the marching kernels take
+    # 32-plane chunks (the second one 8 planes), FP32 tiles 16 x 64 (y: 16,
+    # 16, 8; z: 64, 16) and FP64 tiles 8 x 32 (z: 32, 32, 16); the FP64
+    # level below the finest (20 x 20 x 40) is ragged too
+    "lognormal_mid": (2, (40, 40, 80), {"n_sources": 10}),
 }
 
 # solver parameters per case (on top of the workload's)
-CASE_PARAMS = {"lognormal_tall": {"smoother": 2}, "stromgren_tall": {"smoother": 2}}
+CASE_PARAMS = {"lognormal_tall": {"smoother": 2}, "stromgren_tall": {"smoother": 2},
+               "lognormal_mid": {"smoother": 2}}
 
 
 def case_params(name):
@@ -90,3 +96,22 @@ def errors(g, o, nH, iso, phi_E_rel=1e-20):
     if not iso:
         err["e"] = float(np.max(np.abs(eg - eo) / np.abs(eo)))
     return err
+
+
+_ORACLE_CACHE = {}
+
+
+def cached(key, fn):
+    """Memoise an oracle result for the session (large cases are reused by
+    several tests)."""
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = fn()
+    return _ORACLE_CACHE[key]
+
+
+def elementwise(g, o, floor_rel):
+    """max_P |g - o| / max(|o|, floor_rel * max|o|)."""
+    g = np.asarray(g).ravel()
+    o = np.asarray(o).ravel()
+    fl = floor_rel * np.max(np.abs(o))
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), fl)))

@@ -81,6 +81,54 @@ def test_full_size_step_residual_and_operator_sampled(hip_device, cfg):
     assert sampled["fE"] < 1e-5 and sampled["fn"] < 1e-5 and sampled["fe"] < 1e-5
 
 
+@pytest.mark.parametrize("cfg,checked", [(3, (0, 5, 9)), (4, (5, 14, 24))])
+def test_full_size_late_steps_sampled(hip_device, cfg, checked):
+    """The states the benchmark times: the 512^3 volume advanced through
+    steps 5..24 of its run (the timed window; checked at its first, middle
+    and last step) and the 256^3 volume through its 10 steps, in their own
+    launch configuration (mixed precision).  At each checked step the oracle
+    evaluates, at sampled cells, the residual and the Schur row of the GPU's
+    step from the GPU's checkpoint U^n, as in the first-step test, and every
+    linear solve of the step reached the forcing delta_k = 1e-13 ||f(U_k)||
+    (no solve stopped at the cycle cap)."""
+    import paper_0908_2654_amd as P
+    w = W.get(cfg)
+    op, inp = oracle_inputs(w)
+    t0, dt = inp["t0"], inp["dt"]
+    prm = P.params_from_workload(w)
+    s = P.Solver(prm, device=hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    nH, src = d(inp["nH"]), d(inp["src"])
+    U = tuple(d(inp[k]) for k in ("E", "e", "n"))
+    host = lambda X: X.cpu().numpy()  # noqa: E731
+    for k in range(max(checked) + 1):
+        t = t0 + k * dt
+        Un = tuple(x.clone() for x in U) if k in checked else None
+        st = s.step(t, dt, nH, src, *U)
+        print(f"step {k}: newton={st['newton_its']} cycles={st['lin_its_total']} "
+              f"max/solve={st['lin_its_max']} lin_res_max={st['lin_res_max']:.2e} "
+              f"caps={st['lin_cap_hits']} res={st['res_final']:.2e}", flush=True)
+        assert st["lin_cap_hits"] == 0 and st["lin_res_max"] <= prm.lin_forcing
+        if Un is None:
+            continue
+        fE, fe, fn, nrm = s.residual(t, dt, nH, src, Un, U)
+        assert nrm <= w.newton_tol and nrm == pytest.approx(st["res_final"], rel=1e-6)
+        diag, cf = s.schur_operator(t, dt, nH, src, Un, U)
+        Unh = tuple(host(x) for x in Un)
+        Uh = tuple(host(x) for x in U)
+        inp_k = dict(inp, E=Unh[0], e=Unh[1], n=Unh[2], t0=t)
+        worst, sampled, ncells = check_cells(op, inp_k, Uh, (host(fE), host(fe), host(fn)),
+                                             host(diag), [host(c) for c in cf],
+                                             1.0 - Uh[2] / inp["nH"])
+        print(w.name, "step", k, "cells", ncells, "parity", worst, "oracle residual", sampled,
+              flush=True)
+        assert worst["fE"] < 1e-12 and worst["fn"] < 1e-12 and worst["fe"] < 1e-12
+        assert worst["diag"] < 1e-12 and worst["off"] < 1e-12
+        assert sampled["fE"] < 1e-5 and sampled["fn"] < 1e-5 and sampled["fe"] < 1e-5
+        del fE, fe, fn, diag, cf
+    s.close()
+
+
 def check_cells(op, inp, U, f, diag, cf, xh):
     """Largest differences between the given residual fields f = (fE, fe, fn)
     and Schur operator (diag, cf) of state U and the oracle's, at sampled

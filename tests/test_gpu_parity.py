@@ -5,8 +5,8 @@ and photoheated gas, theta = 1 and theta < 1, FP64 and mixed precision."""
 import numpy as np
 import pytest
 
-from gpu_cases import (CASES, case_params, errors, gpu_trajectory, make_workload,
-                       oracle_inputs, to_dev)
+from gpu_cases import (CASES, cached, case_params, elementwise, errors, gpu_trajectory,
+                       make_workload, oracle_inputs, oracle_trajectory, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -28,8 +28,9 @@ def test_grey_constants_match_oracle(hip_device):
 def _perturbed_state(op, inp, seed=0):
     """U^n = one oracle step from the initial state; U = U^n perturbed."""
     from oracle import newton as ON
-    E1, e1, n1 = ON.step(op, inp["t0"], inp["dt"], inp["nH"], inp["src"], inp["E"], inp["e"],
-                         inp["n"], tol=1e-10)
+    E1, e1, n1 = cached(("first_step", op.dims, op.theta, float(inp["dt"]), float(inp["src"].sum())),
+                        lambda: ON.step(op, inp["t0"], inp["dt"], inp["nH"], inp["src"], inp["E"],
+                                        inp["e"], inp["n"], tol=1e-10))
     rng = np.random.default_rng(seed)
     Ep = E1 * (1 + 0.2 * rng.standard_normal(E1.shape)) + 1e-3 * np.max(E1) * rng.random(E1.shape)
     npert = np.clip(n1 * (1 + 0.1 * rng.standard_normal(n1.shape)), 0, inp["nH"])
@@ -130,31 +131,39 @@ def test_schur_operator_parity(hip_device, case):
     assert off_err < 1e-12 and diag_err < 1e-12
 
 
+def _schur_problem(case):
+    """Oracle Schur operator at a locally consistent perturbed state, a
+    random right-hand side and the oracle's solution (cached per case)."""
+    from oracle import model as OM, newton as ON
+
+    def make():
+        w = make_workload(case)
+        op, inp = oracle_inputs(w)
+        Un, U = _perturbed_state(op, inp, seed=1)
+        # a locally consistent state, as Newton sees it
+        t, dt = inp["t0"] + inp["dt"], inp["dt"]
+        ctx = OM.make_context(op, t, dt, inp["nH"], inp["src"], *Un)
+        n_loc, e_loc = ON.local_solve(op, ctx, U[0], U[2], U[1])
+        e_loc = Un[1] if op.isothermal else e_loc
+        U = (U[0], e_loc, n_loc)
+        ee = None if op.isothermal else U[1]
+        f = OM.residual(op, ctx, U[0], ee, U[2])
+        loc = ON.local_jacobian(op, ctx, U[0], ee, U[2])
+        JEE, JEn = ON.radiation_jacobian(op, ctx, U[0], U[2])
+        S, _, _, _ = ON.schur_operator(op, loc, JEE, JEn, f[1], f[2], f[0])
+        b = np.random.default_rng(3).standard_normal(op.ncells)
+        x_ref = ON.solve_spd(S.tocsr(), b)
+        return w, op, inp, Un, U, t, dt, b, x_ref
+    return cached(("schur", case), make)
+
+
 @pytest.mark.parametrize("krylov", [1, 0])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("case", ["stromgren16", "lognormal_ragged", "outflow_corner",
-                                  "lognormal_tall", "stromgren_tall"])
+                                  "lognormal_tall", "stromgren_tall", "lognormal_mid"])
 def test_schur_solve_parity(hip_device, case, precision, krylov):
-    import scipy.sparse.linalg as spla
-
     import paper_0908_2654_amd as P
-    from oracle import model as OM, newton as ON
-    w = make_workload(case)
-    op, inp = oracle_inputs(w)
-    Un, U = _perturbed_state(op, inp, seed=1)
-    # a locally consistent state, as Newton sees it
-    t, dt = inp["t0"] + inp["dt"], inp["dt"]
-    ctx = OM.make_context(op, t, dt, inp["nH"], inp["src"], *Un)
-    n_loc, e_loc = ON.local_solve(op, ctx, U[0], U[2], U[1])
-    e_loc = Un[1] if op.isothermal else e_loc
-    U = (U[0], e_loc, n_loc)
-    ee = None if op.isothermal else U[1]
-    f = OM.residual(op, ctx, U[0], ee, U[2])
-    loc = ON.local_jacobian(op, ctx, U[0], ee, U[2])
-    JEE, JEn = ON.radiation_jacobian(op, ctx, U[0], U[2])
-    S, _, _, _ = ON.schur_operator(op, loc, JEE, JEn, f[1], f[2], f[0])
-    b = np.random.default_rng(3).standard_normal(op.ncells)
-    x_ref = spla.spsolve(S.tocsc(), b)
+    w, op, inp, Un, U, t, dt, b, x_ref = _schur_problem(case)
     s = P.Solver(P.params_from_workload(w, precision=precision, krylov=krylov,
                                         **case_params(case)), device=hip_device)
     d = lambda a: to_dev(a, hip_device)  # noqa: E731
@@ -164,21 +173,28 @@ def test_schur_solve_parity(hip_device, case, precision, krylov):
     s.close()
     x = x.cpu().numpy().ravel()
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
-    print(f"{case} prec={precision} krylov={krylov}: its={its} relres={rr:.2e} err={err:.2e}")
+    err_el = elementwise(x, x_ref, 1e-6)
+    print(f"{case} prec={precision} krylov={krylov}: its={its} relres={rr:.2e} err={err:.2e} "
+          f"elementwise={err_el:.2e}")
     assert rr < 1e-12
     assert err < 1e-10
+    assert err_el < 1e-9
 
 
 TRAJ = [("stromgren16", 20), ("lognormal_ragged", 2), ("eds_cooling16", 3),
         ("outflow_corner", 3), ("theta06_smalldt", 2), ("lognormal_tall", 2),
-        ("stromgren_tall", 3)]
+        ("stromgren_tall", 3), ("lognormal_mid", 1)]
+
+
+def _oracle_traj(case, op, inp, nsteps, tol):
+    return cached(("traj", case, nsteps, tol), lambda: oracle_trajectory(op, inp, nsteps, tol=tol))
 
 
 @pytest.mark.parametrize("case,nsteps", TRAJ)
 def test_step_parity_fp64(hip_device, case, nsteps):
     w = make_workload(case)
     op, inp = oracle_inputs(w, newton_tol=1e-12)
-    o, ost = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    o, ost = _oracle_traj(case, op, inp, nsteps, 1e-12)
     g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=0,
                             **case_params(case))
     err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
@@ -189,7 +205,7 @@ def test_step_parity_fp64(hip_device, case, nsteps):
 
 
 MIXED = [("stromgren16", 5), ("lognormal_ragged", 2), ("eds_cooling16", 2),
-         ("lognormal_tall", 2)]
+         ("lognormal_tall", 2), ("lognormal_mid", 1)]
 
 
 @pytest.mark.parametrize("case,nsteps", MIXED)
@@ -198,7 +214,7 @@ def test_step_parity_mixed(hip_device, case, nsteps):
     Newton is converged as tightly as in the FP64 parity test."""
     w = make_workload(case)
     op, inp = oracle_inputs(w, newton_tol=1e-12)
-    o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    o, _ = _oracle_traj(case, op, inp, nsteps, 1e-12)
     g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-12, precision=1,
                             **case_params(case))
     err = errors(g, o, inp["nH"], op.isothermal, phi_E_rel=1e-12)
@@ -215,7 +231,7 @@ def test_step_mixed_at_timed_tolerance(hip_device, case, nsteps):
     the tightly converged oracle only by the Newton truncation."""
     w = make_workload(case)
     op, inp = oracle_inputs(w, newton_tol=1e-12)
-    o, _ = __import__("gpu_cases").oracle_trajectory(op, inp, nsteps, tol=1e-12)
+    o, _ = _oracle_traj(case, op, inp, nsteps, 1e-12)
     res, out = {}, {}
     for prec in (0, 1):
         g, gst = gpu_trajectory(w, inp, nsteps, dev=hip_device, newton_tol=1e-8, precision=prec,
@@ -251,11 +267,14 @@ def test_kernel_timing_does_not_change_results(hip_device):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("case", ["lognormal_tall", "stromgren_tall"])
+@pytest.mark.parametrize("case", ["lognormal_tall", "stromgren_tall", "lognormal_mid"])
 def test_fused_sweep_matches_colour_sweeps(hip_device, case, precision):
-    """smoother=2 (both colours in one marching launch) and smoother=1 (one
-    launch per colour) run the same red-black iteration: the same Schur
-    solution to rounding, and the timing classes show which kernel ran."""
+    """smoother=2 (both colours in one marching launch; fused residual and
+    restriction) and smoother=1 (one launch per colour; separate residual and
+    restriction) run the same red-black iteration: one preconditioned
+    iteration gives the same correction cell by cell (the V-cycle's output up
+    to rounding order), the full solve takes the same number of iterations to
+    the same solution, and the timing classes show which kernels ran."""
     import paper_0908_2654_amd as P
     w = make_workload(case)
     op, inp = oracle_inputs(w)
@@ -263,21 +282,30 @@ def test_fused_sweep_matches_colour_sweeps(hip_device, case, precision):
     t, dt = inp["t0"] + inp["dt"], inp["dt"]
     b = np.random.default_rng(9).standard_normal(op.dims)
     d = lambda a: to_dev(a, hip_device)  # noqa: E731
-    xs, kts = {}, {}
+    xs, x1s, itss, kts = {}, {}, {}, {}
     for sm in (1, 2):
         s = P.Solver(P.params_from_workload(w, precision=precision, smoother=sm),
                      device=hip_device)
+        args = (t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)), tuple(map(d, U)), d(b))
+        x1, _, _ = s.schur_solve(*args, rel_tol=1e-13, max_it=1)
+        x1s[sm] = x1.cpu().numpy()
         s.set_kernel_timing(True)
-        x, its, rr = s.schur_solve(t, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
-                                   tuple(map(d, U)), d(b), rel_tol=1e-13, max_it=300)
+        x, its, rr = s.schur_solve(*args, rel_tol=1e-13, max_it=300)
         kts[sm] = s.kernel_timing()
         s.close()
         assert rr < 1e-12
         xs[sm] = x.cpu().numpy()
+        itss[sm] = its
         print(case, precision, "smoother", sm, its, rr)
+    one = elementwise(x1s[2], x1s[1], 1e-6)
+    print(case, precision, "one cycle, elementwise", one)
+    assert one < (1e-4 if precision == 1 else 1e-11)
+    assert abs(itss[2] - itss[1]) <= (1 if precision == 1 else 0)
     assert np.linalg.norm(xs[2] - xs[1]) / np.linalg.norm(xs[1]) < 1e-11
     assert kts[1]["rbgs_fine"][1] == 0 and kts[1]["rbgs_fine_colour"][1] > 0
     assert kts[2]["rbgs_fine"][1] > 0 and kts[2]["rbgs_fine_colour"][1] == 0
+    assert kts[1]["mg_residual_fine"][1] > 0 and kts[1]["restrict_fine"][1] > 0
+    assert kts[2]["restrict_fine"][1] == 0
 
 
 # ---------------------------------------------------------------------------
@@ -296,8 +324,6 @@ def test_adjoint_step_parity(hip_device, case, precision):
     from oracle import adjoint as OA, newton as ON
     w = make_workload(case)
     op, inp = oracle_inputs(w)
-    if w.sources == "random" and op.ncells > 8000:
-        pytest.skip("oracle transpose solve too large")
     t0, dt = inp["t0"], inp["dt"]
     Un = ON.step(op, t0, dt, inp["nH"], inp["src"], inp["E"], inp["e"], inp["n"], tol=1e-12)
     U1 = ON.step(op, t0 + dt, dt, inp["nH"], inp["src"], *Un, tol=1e-12)
@@ -315,14 +341,16 @@ def test_adjoint_step_parity(hip_device, case, precision):
     st = s.adjoint_step(t0 + dt, dt, d(inp["nH"]), d(inp["src"]), tuple(map(d, Un)),
                         tuple(map(d, U1)), (lE, le, ln), g_src, g_nH)
     s.close()
-    rel = lambda g, o: float(np.linalg.norm(g - o) / np.linalg.norm(o))  # noqa: E731
-    errs = {"lE": rel(lE.cpu().numpy(), oE), "ln": rel(ln.cpu().numpy(), on),
-            "g_src": rel(g_src.cpu().numpy(), ogs), "g_nH": rel(g_nH.cpu().numpy(), ogh)}
+    # cell by cell, with a floor of 1e-6 of the largest entry (the adjoint
+    # of dark cells is many orders below that of the ionised region)
+    el = lambda g, o: elementwise(g.cpu().numpy(), o, 1e-6)  # noqa: E731
+    errs = {"lE": el(lE, oE), "ln": el(ln, on), "g_src": el(g_src, ogs), "g_nH": el(g_nH, ogh)}
     if not op.isothermal:
-        errs["le"] = rel(le.cpu().numpy(), oe)
-    print(case, precision, st["lin_its_total"], errs)
+        errs["le"] = el(le, oe)
+    print(case, precision, st["lin_its_total"], st["lin_cap_hits"], errs)
+    assert st["lin_cap_hits"] == 0
     for k, v in errs.items():
-        assert v < 1e-9, (k, v)
+        assert v < 1e-8, (k, v)
 
 
 def torch_zeros(dims, dev):
@@ -354,9 +382,8 @@ def test_autograd_gradient_matches_oracle(hip_device, case, nsteps):
     J = (1.0 - n / nH).mean()
     gs, gh = torch.autograd.grad(J, (src, nH))
     s.close()
-    rel = lambda g, o: float(np.linalg.norm(g - o) / np.linalg.norm(o))  # noqa: E731
-    print(case, "J", J.item(), J_o, "g_src", rel(gs.cpu().numpy(), gs_o), "g_nH",
-          rel(gh.cpu().numpy(), gh_o))
+    es = elementwise(gs.cpu().numpy(), gs_o, 1e-6)
+    eh = elementwise(gh.cpu().numpy(), gh_o, 1e-6)
+    print(case, "J", J.item(), J_o, "g_src", es, "g_nH", eh)
     assert J.item() == pytest.approx(J_o, rel=1e-10)
-    assert rel(gs.cpu().numpy(), gs_o) < 1e-8
-    assert rel(gh.cpu().numpy(), gh_o) < 1e-8
+    assert es < 1e-7 and eh < 1e-7
