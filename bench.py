@@ -53,6 +53,55 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
     }.get(kind)
 
 
+def linear_iteration_bytes(T):
+    """Algorithmic bytes per fine cell of one preconditioned CG iteration:
+    the V(2,2) cycle on the finest level (three plain fused sweeps, the last
+    sweep with the CG dot products, the fused residual + restriction and
+    the prolongation), the levels below it (the same work on N/8 + N/64 +
+    ... = N/7 cells, no dot products), the direction kernel (S p and the
+    folded x update) and the update kernel."""
+    b = algorithmic_bytes_per_cell
+    fine = 3 * b("rbgs_fine", T) + b("rbgs_fine_dots", T) + b("mg_residual_fine", T) \
+        + b("prolong_fine", T)
+    coarse = (4 * b("rbgs_fine", T) + b("mg_residual_fine", T) + b("prolong_fine", T)) / 7.0
+    return fine + coarse + b("pcg_direction", T) + b("pcg_update", T)
+
+
+def step_bytes_per_cell(st, T, iso=False):
+    """Algorithmic bytes per cell of one implicit step from its statistics:
+    U^n copied in and the result copied out (3 fields each way), the face
+    limiter, one local solve + residual per evaluation (the start, one trial
+    per Newton iteration and one per line-search cut), the coarse-level
+    operators per Newton iteration (diagonal of N/7 cells: shift in, diag
+    out) and every linear iteration."""
+    b = algorithmic_bytes_per_cell
+    evals = 1 + st["newton_its"] + st["ls_cuts"]
+    copies = 2 * 3 * 2 * 8
+    return (copies + b("step_setup", T) + evals * (b("local_solve", T, iso) + b("residual_schur", T))
+            + st["newton_its"] * (3 * T / 7.0) + st["lin_its_total"] * linear_iteration_bytes(T))
+
+
+def host_description():
+    """CPU of the host: logical CPUs, model name and the BLAS thread pools."""
+    import platform
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "threads": i.get("num_threads")}
+                for i in threadpool_info()]
+    except Exception:  # threadpoolctl missing
+        blas = None
+    return {"os_cpu_count": os.cpu_count(), "model": model, "blas_pools": blas}
+
+
 def measured_traffic(kind, workload):
     """HBM bytes per launch of `kind` from the committed counter record, or
     None when there is none or the kernels have changed since it was taken."""
@@ -98,8 +147,9 @@ def run_path(P, w, prec, inp, state, t_start, dt, steps, timing, adjoint=False):
             torch.cuda.synchronize()
             t_ck += time.perf_counter() - tc
         log(f"  prec={prec} step {k}: newton={stats[-1]['newton_its']} "
-            f"vcycles={stats[-1]['lin_its_total']} res={stats[-1]['res_final']:.2e} "
-            f"gpu_ms={stats[-1]['t_ms'][0]:.1f}")
+            f"vcycles={stats[-1]['lin_its_total']} (max {stats[-1]['lin_its_max']}/solve, "
+            f"caps {stats[-1]['lin_cap_hits']}, lin_res {stats[-1]['lin_res_max']:.1e}) "
+            f"res={stats[-1]['res_final']:.2e} gpu_ms={stats[-1]['t_ms'][0]:.1f}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0 - t_ck
     kt = s.kernel_timing() if timing else None
@@ -124,6 +174,8 @@ def run_path(P, w, prec, inp, state, t_start, dt, steps, timing, adjoint=False):
         adj = {"ms_per_step": round(1e3 * wa / steps, 2),
                "ratio_to_forward": round(wa / wall, 3),
                "vcycles": [a["lin_its_total"] for a in ast],
+               "lin_res_max": max(a["lin_res_max"] for a in ast),
+               "lin_target": 1e-13,
                "objective": "mean x_HII after the timed steps; gradients wrt src and n_H",
                "finite": bool(torch.isfinite(g_src).all().item() and torch.isfinite(g_nH).all().item())}
         log(f"  adjoint: {adj['ms_per_step']} ms/step, ratio {adj['ratio_to_forward']}")
@@ -184,35 +236,44 @@ def run_advection(P, w, inp, state, t, dt, reps=3):
                          "launches": cnt}}
 
 
-def cpu_baseline(w, nH_full, t0, dt, sub=64):
+def cpu_baseline(w, nH_full, state, t, dt, sub=64):
     """The oracle, as it stands, on a bounded sample: one implicit step of a
-    sub^3 periodic sub-volume cut from the same workload (same cells, same
-    density and sources inside it, same time and step)."""
+    sub^3 block cut from a checkpoint of the timed window (the GPU state at
+    the start of the first timed step: same cells, density, sources, fields,
+    time and step), closed as a periodic box; BLAS limited to one thread,
+    which is what NumPy's elementwise work and SciPy's sparse solvers use."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import workloads as W
     from oracle import model as OM, newton as ON
     ws = W.get(w)
     ws.dims = (sub, sub, sub)
     ws.box_comoving_cm = w.box_comoving_cm * sub / w.dims[0]
-    nH = np.ascontiguousarray(nH_full[:sub, :sub, :sub])
-    Qfull = W.photon_rate_field(w)
-    Q = np.ascontiguousarray(Qfull[:sub, :sub, :sub])
-    op = OM.params_from_workload(ws, newton_tol=1e-8)
+    ws.bc = (W.BC_PERIODIC,) * 6
+    cut = (slice(0, sub),) * 3
+    nH = np.ascontiguousarray(nH_full[cut])
+    Q = np.ascontiguousarray(W.photon_rate_field(w)[cut])
+    E, e, n = (np.ascontiguousarray(x[cut].cpu().numpy()) for x in state)
+    # the limiter floor of the whole box, R_min = 1 / (a_n L_box)
+    a_n = OM.params_from_workload(w).cosmo.a(t)
+    op = OM.params_from_workload(ws, newton_tol=1e-8, R_min=1.0 / (a_n * w.box_comoving_cm))
     src = OM.source_field(op, Q)
-    E, e, n = OM.initial_state(op, nH, ws.x0, ws.T0, ws.E0)
-    t1 = time.perf_counter()
     st = {}
-    ON.step(op, t0, dt, nH, src, E, e, n, stats=st)
-    el = time.perf_counter() - t1
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        ON.step(op, t, dt, nH, src, E, e, n, stats=st)
+        el = time.perf_counter() - t1
     return {
         "value": sub ** 3 / el / 1e6,
         "unit": "Mcell-updates/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"one implicit step (Newton to ||f|| <= 1e-8, {st['newton_its']} iterations) of a "
-                  f"{sub}^3 sub-volume of the same workload (same density, sources, t and dt), "
-                  f"{el:.1f} s of CPU time, single-threaded NumPy/SciPy",
+                  f"{sub}^3 block of the GPU state at the start of the first timed step (same "
+                  f"density, sources, fields, t and dt; the block closed periodically), "
+                  f"{el:.1f} s on one thread (BLAS limited to 1)",
+        "host": host_description(),
     }
 
 
@@ -312,9 +373,13 @@ def main():
     fp64 = None
     if not args.no_fp64:
         wall_d, st_d, _, out_d, _ = run_path(P, w, 0, inp, state, t_start, dt, args.steps, False)
+        bytes_d = [step_bytes_per_cell(x, 8, w.isothermal) for x in st_d]
         fp64 = {"value": N * args.steps / wall_d / 1e6, "ms_per_step": 1e3 * wall_d / args.steps,
-                "newton_its": [s["newton_its"] for s in st_d],
-                "vcycles": [s["lin_its_total"] for s in st_d]}
+                "newton_its": [x["newton_its"] for x in st_d],
+                "vcycles": [x["lin_its_total"] for x in st_d],
+                "lin_res_max": max(x["lin_res_max"] for x in st_d),
+                "lin_cap_hits": sum(x["lin_cap_hits"] for x in st_d),
+                "step_hbm_frac": round(sum(bytes_d) * N / wall_d / 1e9 / HBM_PEAK_GBS, 4)}
         dE = (out_m[0] - out_d[0]).abs().max().item() / out_d[0].abs().max().item()
         dx = ((out_m[2] - out_d[2]).abs() / inp["nH"]).max().item()
         fp64["max_diff_vs_mixed"] = {"E_rel_to_max": dE, "x_HII_abs": dx}
@@ -355,8 +420,15 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(w, nH_host, t_start, dt)
+        cpu = cpu_baseline(w, nH_host, state, t_start, dt, sub=min(64, w.dims[0]))
         log(f"cpu baseline: {cpu['value']:.4f} Mcell-updates/s")
+
+    # whole-step algorithmic bytes (from each step's own statistics) and the
+    # step-level HBM fraction over the timed steps
+    bytes_m = [step_bytes_per_cell(x, 4, w.isothermal) for x in st_m]
+    step_hbm = sum(bytes_m) * N / wall_m / 1e9
+    gpu_ms = sorted(x["t_ms"][0] for x in st_m)
+    phases = [round(sum(x["t_ms"][q] for x in st_m) / len(st_m), 2) for q in range(1, 6)]
 
     line = {
         "metric": "Mcell-updates/s per implicit step at 1e-8 residual: FP32-MG+refine vs FP64",
@@ -373,9 +445,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.dims), "sources": w.n_sources,
                    "steps_of_run": f"{args.warmup}..{args.warmup + args.steps - 1} of {nsteps}",
-                   "newton_tol": 1e-8, "lin_forcing": 1e-13, "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner",
-                   "newton_its": [s["newton_its"] for s in st_m],
-                   "vcycles": [s["lin_its_total"] for s in st_m]},
+                   "newton_tol": 1e-8, "lin_forcing": 1e-13,
+                   "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner",
+                   "lin_max_it": 500},
+        "per_step": {"newton_its": [x["newton_its"] for x in st_m],
+                     "vcycles": [x["lin_its_total"] for x in st_m],
+                     "vcycles_max_per_solve": [x["lin_its_max"] for x in st_m],
+                     "lin_res_max": [float(f"{x['lin_res_max']:.3g}") for x in st_m],
+                     "lin_cap_hits": [x["lin_cap_hits"] for x in st_m],
+                     "res_final": [float(f"{x['res_final']:.3g}") for x in st_m],
+                     "forcing_reached": all(x["lin_cap_hits"] == 0 and x["lin_res_max"] <= 1e-13
+                                            for x in st_m),
+                     "gpu_ms_median": round(gpu_ms[len(gpu_ms) // 2], 2),
+                     "phase_ms_mean": dict(zip(["setup", "local_residual", "coarse_setup",
+                                                "vcycles", "outer_linear"], phases)),
+                     "step_bytes_per_cell": [round(b, 1) for b in bytes_m],
+                     "step_hbm_GBs": round(step_hbm, 1),
+                     "step_hbm_frac": round(step_hbm / HBM_PEAK_GBS, 4)},
         "fp64_path": fp64,
         "roofline": roof,
         "adjoint": adj,
