@@ -267,6 +267,26 @@ rh_status rh_residual(rh_handle* h, double t_n_s, double dt_s, const double* nH,
                       const double* nHI, double* fE, double* fe, double* fn,
                       double* norm_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as rh_residual, with no handle and no workspace.  p as for
+ * rh_setup (validated the same way); hip_stream a hipStream_t (NULL = the
+ * default stream) of the current device.  The face coefficients, local
+ * terms and reduction partials live in a static device array of the
+ * library (about 18.3 MiB per GPU, held until the process ends), so grids
+ * are limited to 64^3 = 262144 cells (larger: RH_EINVAL, nothing
+ * enqueued).  Calls on one GPU share that array: calls that overlap in
+ * time on the same GPU (other host threads or streams) race and must be
+ * serialised by the caller; nothing in the array needs to start at zero
+ * (every value a call reads was written earlier in that call).  Calls no
+ * hipMalloc or hipFree (the first call on a device looks up the array's
+ * address); synchronises hip_stream twice.  Errors: rh_last_error(NULL). */
+rh_status rh_residual_noalloc(const rh_params* p, void* hip_stream, double t_n_s, double dt_s,
+                              const double* nH, const double* src, const double* E_n,
+                              const double* e_n, const double* nHI_n, const double* E,
+                              const double* e, const double* nHI, double* fE, double* fe,
+                              double* fn, double* norm_out);
+
 /* Write the Schur operator S of the Newton system at U = (E, e, nHI) of the
  * step from U^n (Algorithm section: the radiation equation after the local
  * unknowns are eliminated), the operator rh_schur_solve inverts:

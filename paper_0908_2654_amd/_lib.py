@@ -98,6 +98,8 @@ SIGNATURES = {
                          ctypes.POINTER(RhAdvectStats)]),
     "rh_residual": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, ctypes.POINTER(_f64)]),
+    "rh_residual_noalloc": (_i32, [_PP, _vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _vp, _vp, ctypes.POINTER(_f64)]),
     "rh_schur_solve": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                               _vp, _vp, _f64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_f64)]),
     "rh_schur_operator": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

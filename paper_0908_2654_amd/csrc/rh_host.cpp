@@ -15,7 +15,13 @@ using namespace rh;
 
 namespace {
 
-thread_local std::string g_last_error;
+// message of the last failed handle-free call on this thread (a fixed
+// buffer: setting it allocates nothing)
+thread_local char g_last_error[256];
+
+void set_global_error(const char* msg) {
+  std::snprintf(g_last_error, sizeof g_last_error, "%s", msg);
+}
 
 // ---------------------------------------------------------------------------
 // grey constants of the T_B blackbody above h nu_0 (equation grey_definition)
@@ -137,6 +143,12 @@ void cosmo_at(const rh_params& p, double t, double& a, double& H) {
     a = std::cbrt(p.Omega_m / p.Omega_L) * std::pow(s, 2.0 / 3.0);
     H = H0 * std::sqrt(p.Omega_m / (a * a * a) + p.Omega_L);
   }
+}
+
+// Compton cooling coefficient 4 sigma_T a_rad k_B T_cmb0^4 / (m_e c) (the
+// rate per electron and per kelvin of T - T_cmb at z = 0; scales as (1+z)^4).
+double compton_coefficient() {
+  return 4.0 * kSigmaT * kARad * kKB * std::pow(kTcmb0, 4) / (kME * kC);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,36 +396,38 @@ rh_status fail(rh_handle* h, rh_status st, const std::string& msg) {
   return st;
 }
 
-StepK make_step(rh_handle* h, double t_n, double dt) {
-  const rh_params& p = h->p;
+StepK make_step_from(const rh_params& p, const Grey& g, double t_n, double dt) {
+  const double hcell = p.box_comoving_cm / p.nx;
   StepK k;
   k.nx = p.nx; k.ny = p.ny; k.nz = p.nz;
-  k.N = h->N;
+  k.N = (long long)p.nx * p.ny * p.nz;
   for (int f = 0; f < 6; ++f) k.bc[f] = p.bc[f];
   k.iso = p.isothermal ? 1 : 0;
   k.rates = p.rates;
   k.cooling = p.cooling_mask;
   k.theta_lt1 = p.theta < 1.0 ? 1 : 0;
-  k.h = h->h;
+  k.h = hcell;
   k.dt = dt;
   k.theta = p.theta;
   cosmo_at(p, t_n, k.a_n, k.H_n);
   cosmo_at(p, t_n + dt, k.a_1, k.H_1);
-  k.sigma_E = h->g.sigma_E;
-  k.K_Gamma = h->g.K_Gamma;
-  k.K_G = h->g.K_G;
-  k.hnu0 = h->g.hnu0;
+  k.sigma_E = g.sigma_E;
+  k.K_Gamma = g.K_Gamma;
+  k.K_G = g.K_G;
+  k.hnu0 = g.hnu0;
   k.T_iso = p.T_iso_K;
   k.alphaB = p.alphaB_const;
   k.gamma = p.gamma;
-  k.compton = h->compton;
+  k.compton = compton_coefficient();
   k.E_floor = p.E_floor;
   k.R_min = p.R_min > 0 ? p.R_min : 1.0 / (k.a_n * p.box_comoving_cm);
-  k.cf_scale = dt * p.theta / (k.a_1 * k.a_1 * h->h * h->h);
+  k.cf_scale = dt * p.theta / (k.a_1 * k.a_1 * hcell * hcell);
   k.expl_ratio = (1.0 - p.theta) / p.theta * (k.a_1 * k.a_1) / (k.a_n * k.a_n);
   k.E_s = 1.0;
   return k;
 }
+
+StepK make_step(rh_handle* h, double t_n, double dt) { return make_step_from(h->p, h->g, t_n, dt); }
 
 void flush_timing(rh_handle* h) {
   for (int i = 0; i < h->npool; ++i) {
@@ -907,6 +921,20 @@ rh_status copy_state(rh_handle* h, double* E, double* e, double* n, const double
 
 }  // namespace
 
+// Helpers of the handle-free entry point (rh_noalloc.hip).
+namespace rh {
+bool params_valid(const rh_params* p, char* err, size_t n) {
+  std::string e;
+  if (validate(p, e)) return true;
+  std::snprintf(err, n, "%s", e.c_str());
+  return false;
+}
+StepK step_scalars(const rh_params& p, double t_n, double dt) {
+  return make_step_from(p, grey_constants(p), t_n, dt);
+}
+void set_last_error(const char* msg) { set_global_error(msg); }
+}  // namespace rh
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -951,7 +979,7 @@ void rh_default_params(rh_params* p) {
 size_t rh_workspace_bytes(const rh_params* p) {
   std::string err;
   if (!validate(p, err)) {
-    g_last_error = err;
+    set_global_error(err.c_str());
     return 0;
   }
   Plan pl;
@@ -964,17 +992,17 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
                    rh_handle** out) {
   std::string err;
   if (!out) {
-    g_last_error = "out is NULL";
+    set_global_error("out is NULL");
     return RH_EINVAL;
   }
   *out = nullptr;
   if (!validate(p, err)) {
-    g_last_error = err;
+    set_global_error(err.c_str());
     return RH_EINVAL;
   }
   const size_t need = rh_workspace_bytes(p);
   if (!workspace || ws_bytes < need) {
-    g_last_error = "workspace missing or smaller than rh_workspace_bytes";
+    set_global_error("workspace missing or smaller than rh_workspace_bytes");
     return workspace ? RH_ENOMEM : RH_EINVAL;
   }
   rh_handle* h = new rh_handle();
@@ -982,7 +1010,7 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
   plan_levels(*p, h->plan, err);
   h->g = grey_constants(*p);
   h->h = p->box_comoving_cm / p->nx;
-  h->compton = 4.0 * kSigmaT * kARad * kKB * std::pow(kTcmb0, 4) / (kME * kC);
+  h->compton = compton_coefficient();
   h->N = (long long)p->nx * p->ny * p->nz;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = reinterpret_cast<char*>(workspace);
@@ -1013,8 +1041,8 @@ rh_status rh_setup(const rh_params* p, void* workspace, size_t ws_bytes, void* h
                            "hipMemsetAsync (reduction counts)"};
     int i = 0;
     while (es[i] == hipSuccess) ++i;
-    g_last_error = std::string("HIP initialisation failed: ") + what[i] + ": " +
-                   hipGetErrorString(es[i]);
+    set_global_error((std::string("HIP initialisation failed: ") + what[i] + ": " +
+                      hipGetErrorString(es[i])).c_str());
     delete h;
     return RH_EHIP;
   }
@@ -1591,7 +1619,7 @@ rh_status rh_cosmic_time(const rh_params* p, double a, double* t) {
 }
 
 const char* rh_last_error(const rh_handle* h) {
-  return h ? h->err.c_str() : g_last_error.c_str();
+  return h ? h->err.c_str() : g_last_error;
 }
 
 void rh_destroy(rh_handle* h) {

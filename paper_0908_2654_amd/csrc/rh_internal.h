@@ -87,6 +87,15 @@ constexpr unsigned kAllSlots = (1u << RS_COUNT) - 1;
 constexpr unsigned slot_bit(int s) { return 1u << s; }
 
 
+// ---- host helpers (rh_host.cpp) -------------------------------------------
+// Parameter validation as rh_setup does it (message into err on failure).
+bool params_valid(const rh_params* p, char* err, size_t n);
+// The per-step scalars of a step from t_n over dt (grey constants,
+// expansion factors, limiter floor, coefficient scales); E_s = 1.
+StepK step_scalars(const rh_params& p, double t_n, double dt);
+// Message returned by rh_last_error(NULL) on this thread.
+void set_last_error(const char* msg);
+
 // ---- launchers (rh_kernels.hip) ------------------------------------------
 // Weighted change of a step and its most negative E: partial sums of
 // (dE/E_s)^2 + (de/e^n)^2 + (dn/n_H)^2 (RS_CHG2; no e term when e is null)

@@ -82,6 +82,24 @@ def cosmic_time(p: RhParams, a: float) -> float:
     return t.value
 
 
+def residual_noalloc(params: RhParams, t, dt, nH, src, Un, U, out, stream=None) -> float:
+    """f(U) of the step from U^n through rh_residual_noalloc (no handle, no
+    workspace: the library's static scratch; grids up to 64^3 cells).
+    out = (fE, fe, fn) preallocated tensors (entries may be None); returns
+    the RMS norm."""
+    En, en, nn = Un
+    E, e, n = U
+    fE, fe, fn = out
+    st = torch.cuda.current_stream() if stream is None else stream
+    norm = _F64()
+    s = lib.rh_residual_noalloc(ctypes.byref(params), ctypes.c_void_p(st.cuda_stream), float(t),
+                                float(dt), _ptr(nH), _ptr(src), _ptr(En), _ptr(en), _ptr(nn),
+                                _ptr(E), _ptr(e), _ptr(n), _ptr(fE), _ptr(fe), _ptr(fn),
+                                ctypes.byref(norm))
+    check(s)
+    return norm.value
+
+
 class Solver:
     """Owns a workspace tensor and a library handle on one device/stream."""
 
