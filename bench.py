@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--mg-post", type=int, default=2)
     ap.add_argument("--smoother", type=int, default=0,
                     help="0 auto, 1 one launch per colour, 2 fused sweep wherever it fits")
+    ap.add_argument("--block-radius", type=int, default=2,
+                    help="box radius of the block smoother around sources (0 off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -339,11 +341,12 @@ def main():
         print(json.dumps({"copy_bytes": 4 << 28, "launches": 3}))
         return
     w = W.get(args.config)
-    MG.update(mg_pre=args.mg_pre, mg_post=args.mg_post, smoother=args.smoother)
+    MG.update(mg_pre=args.mg_pre, mg_post=args.mg_post, smoother=args.smoother,
+              mg_block_radius=args.block_radius)
     log(f"workload {w.name} dims={w.dims}: generating inputs")
     tg = time.perf_counter()
     nH_host = W.density_field(w)
-    prm = P.params_from_workload(w, precision=1)
+    prm = P.params_from_workload(w, precision=1, **MG)
     s0 = P.Solver(prm, device=dev)
     inp = device_inputs(w, s0, nH_host=nH_host)
     t0, dt, nsteps = schedule(w, prm)
@@ -446,7 +449,9 @@ def main():
         "config": {"workload": w.name, "grid": list(w.dims), "sources": w.n_sources,
                    "steps_of_run": f"{args.warmup}..{args.warmup + args.steps - 1} of {nsteps}",
                    "newton_tol": 1e-8, "lin_forcing": 1e-13,
-                   "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner",
+                   "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner"
+                            + (f", source boxes of radius {args.block_radius} on 2 levels"
+                               if args.block_radius else ""),
                    "lin_max_it": 500},
         "per_step": {"newton_its": [x["newton_its"] for x in st_m],
                      "vcycles": [x["lin_its_total"] for x in st_m],

@@ -115,6 +115,21 @@ typedef struct rh_params {
                                /* launches on every level their tiles fit (FP32 levels:  */
                                /* nz >= 64, ny >= 16; FP64: nz >= 32, ny >= 8; nx >= 4). */
                                /* Same iterates up to rounding order.                    */
+  int32_t mg_block_radius;     /* block smoother around point sources (default 2; 0 off,  */
+                               /* at most 2): on the finest mg_block_levels levels the   */
+                               /* V-cycle also solves the operator exactly on a box of   */
+                               /* (2R+1)^3 cells around each cell holding a source (src  */
+                               /* > 0; on coarse levels the cell containing it), after   */
+                               /* the pre-smoothing and before the post-smoothing.  The  */
+                               /* face-limited diffusion is strongly anisotropic around  */
+                               /* sources (radial faces see the steep fall-off of E,     */
+                               /* tangential ones R = R_min), and those modes need it.   */
+  int32_t mg_block_levels;     /* levels with source boxes (default 2, at most 4)        */
+  int32_t mg_block_max;        /* most source cells with boxes; 0 (default): one per     */
+                               /* 4096 cells, at least 64, at most 8192.  The workspace  */
+                               /* grows by 4 (FP32) or 8 (FP64) x (2R+1)^6 bytes per box */
+                               /* and level; a step with more source cells runs without  */
+                               /* boxes                                                  */
 } rh_params;
 
 /* Per-step statistics (host memory). */
@@ -140,6 +155,8 @@ typedef struct rh_step_stats {
   int32_t lin_cap_hits;        /* linear solves that stopped without reaching their      */
                                /* target (at lin_max_it, on stagnation or breakdown)     */
   int32_t lin_its_max;         /* most V-cycles in one linear solve of the call          */
+  int32_t source_boxes;        /* boxes of the block smoother on the finest level (0:    */
+                               /* none this step)                                        */
 } rh_step_stats;
 
 /* Statistics of rh_advance (host memory). */
@@ -360,7 +377,9 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
  * a finest level too small for the fused sweep, 15 the last fused sweep of
  * a V-cycle on the finest level when it also forms the conjugate-gradient
  * dot products (class 11 then has no launches), 16 advection substep
- * (rh_advect), 17 its Courant-number reduction.  ms / counts are host arrays
+ * (rh_advect), 17 its Courant-number reduction, 18 block relaxation around the
+ * sources on the finest level, 19 the box inverses of the block smoother
+ * (all levels; block relaxation below the finest level counts in 8).  ms / counts are host arrays
  * (either may be NULL); reset != 0 clears the totals afterwards. */
 rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
                                int32_t reset);

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_PKG, "librh.so")
 KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rbgs_fine",
                   "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
                   "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast",
-                  "rbgs_fine_colour", "rbgs_fine_dots", "advect", "advect_courant"]
+                  "rbgs_fine_colour", "rbgs_fine_dots", "advect", "advect_courant",
+                  "block_relax", "block_inverse"]
 
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",
@@ -46,6 +47,7 @@ class RhParams(ctypes.Structure):
         ("lin_forcing", _f64),
         ("lin_max_it", _i32), ("mg_pre", _i32), ("mg_post", _i32), ("mg_coarse_max", _i32),
         ("krylov", _i32), ("smoother", _i32),
+        ("mg_block_radius", _i32), ("mg_block_levels", _i32), ("mg_block_max", _i32),
     ]
 
 
@@ -55,7 +57,7 @@ class RhStepStats(ctypes.Structure):
         ("local_its_max", _i32),
         ("res0", _f64), ("res_final", _f64), ("lin_res_max", _f64),
         ("t_ms", _f64 * 8),
-        ("lin_cap_hits", _i32), ("lin_its_max", _i32),
+        ("lin_cap_hits", _i32), ("lin_its_max", _i32), ("source_boxes", _i32),
     ]
 
     def as_dict(self):

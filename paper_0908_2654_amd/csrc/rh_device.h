@@ -59,6 +59,24 @@ inline int red_grid(long long N) {
 
 __device__ inline int pmod(int a, int m) { return ((a % m) + m) % m; }
 
+// Neighbour q of cell c along axis d on side s (+1 / -1): false across a
+// non-periodic wall, wrapped across a periodic one.
+__device__ inline bool neighbour(const int (&c)[3], const int (&n)[3], const int* per, int d,
+                                 int s, int (&q)[3]) {
+  q[0] = c[0]; q[1] = c[1]; q[2] = c[2];
+  int v = c[d] + s;
+  if (v < 0) {
+    if (!per[d]) return false;
+    v += n[d];
+  } else if (v >= n[d]) {
+    if (!per[d]) return false;
+    v -= n[d];
+  }
+  q[d] = v;
+  return true;
+}
+
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Give each XCD a contiguous range of tile indices, so tiles that share
 // halo cache lines (neighbours along z come next in tile order) run on the

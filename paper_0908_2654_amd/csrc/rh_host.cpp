@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "rh_internal.h"
 
@@ -222,6 +223,9 @@ bool validate(const rh_params* p, std::string& err) {
   if (p->mg_coarse_max < 1 || p->mg_coarse_max > kCoarseMaxCells) { err = "mg_coarse_max in [1, 512]"; return false; }
   if (p->krylov != 0 && p->krylov != 1) { err = "krylov must be 0 or 1"; return false; }
   if (p->smoother < 0 || p->smoother > 2) { err = "smoother must be 0, 1 or 2"; return false; }
+  if (p->mg_block_radius < 0 || p->mg_block_radius > 2) { err = "mg_block_radius in [0, 2]"; return false; }
+  if (p->mg_block_levels < 0 || p->mg_block_levels > kMaxBlockLevels) { err = "mg_block_levels in [0, 4]"; return false; }
+  if (p->mg_block_max < 0 || p->mg_block_max > (1 << 20)) { err = "mg_block_max in [0, 2^20]"; return false; }
   Plan pl;
   if (!plan_levels(*p, pl, err)) return false;
   return true;
@@ -230,6 +234,14 @@ bool validate(const rh_params* p, std::string& err) {
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
+// Most source cells with boxes: mg_block_max, or when it is 0 one per 4096
+// cells, at least 64 and at most 8192.
+long long block_capacity(const rh_params& p) {
+  if (p.mg_block_max > 0) return p.mg_block_max;
+  const long long N = (long long)p.nx * p.ny * p.nz;
+  return std::min<long long>(8192, std::max<long long>(64, N / 4096));
+}
+
 struct Carver {
   char* base;
   size_t off = 0;
@@ -257,7 +269,7 @@ struct StateBuf {
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
   KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_RBGS0D,
-  KK_ADVECT, KK_ADVECT_C, KK_COUNT
+  KK_ADVECT, KK_ADVECT_C, KK_BLOCK0, KK_BLOCKINV, KK_COUNT
 };
 
 struct rh_handle {
@@ -280,6 +292,18 @@ struct rh_handle {
   // levels
   LevelK<float> L32[kMaxLevels];
   LevelK<double> L64[kMaxLevels];
+  // source-centred boxes of the block smoother (levels 0 .. nblk - 1)
+  int nblk = 0;                        // levels with boxes this step
+  BlockSet<float> B32[kMaxBlockLevels];
+  BlockSet<double> B64[kMaxBlockLevels];
+  int* bstart[kMaxBlockLevels];        // device: box corners (3 ints per box)
+  std::vector<int> bcolour[kMaxBlockLevels];  // colour c: boxes [off[c], off[c+1])
+  int* src_count;                      // device: source cells per scan range
+  int* src_offset;                     // device: their exclusive prefix sums
+  int* src_list;                       // device: source cells in cell order
+  int src_groups = 0;
+  long long src_chunk = 0;
+  int nsrc = 0;                        // source cells of the current step
   double *cA, *cInv;
   float* cInv32;
   double* cInv64;
@@ -379,6 +403,30 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
   h->cInv = cv.take<double>(nc * nc);
   h->cInv32 = mixed ? cv.take<float>(nc * nc) : nullptr;
   h->cInv64 = mixed ? nullptr : cv.take<double>(nc * nc);
+  // block smoother: source scan buffers and, per level with boxes, the box
+  // corners and inverses
+  const int R = p.mg_block_radius;
+  const int blevels = R > 0 ? std::min(p.mg_block_levels, pl.nlev - 1) : 0;
+  h->src_groups = (int)std::min<long long>(4096, (N + kBlock - 1) / kBlock);
+  h->src_chunk = (N + h->src_groups - 1) / h->src_groups;
+  h->src_count = cv.take<int>(h->src_groups);
+  h->src_offset = cv.take<int>(h->src_groups);
+  const long long cap = block_capacity(p);
+  h->src_list = blevels > 0 ? cv.take<int>(cap) : nullptr;
+  for (int l = 0; l < kMaxBlockLevels; ++l) {
+    h->bstart[l] = nullptr;
+    h->B32[l] = BlockSet<float>{};
+    h->B64[l] = BlockSet<double>{};
+  }
+  for (int l = 0; l < blevels; ++l) {
+    int m = 1;
+    for (int a = 0; a < 3; ++a) m *= std::min(2 * R + 1, pl.dims[l][a]);
+    h->bstart[l] = cv.take<int>((size_t)3 * cap);
+    if (mixed)
+      h->B32[l].inv = cv.take<float>((size_t)cap * m * m);
+    else
+      h->B64[l].inv = cv.take<double>((size_t)cap * m * m);
+  }
   return cv.off + 256;
 }
 
@@ -523,6 +571,8 @@ rh_status sync_reductions(rh_handle* h, unsigned mask) {
 
 double nvars(const rh_handle* h) { return h->p.isothermal ? 2.0 : 3.0; }
 
+rh_status plan_blocks(rh_handle* h, const double* src);
+
 // Per-step setup: U^n copies are already in En/en/nn.
 rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
   const bool mixed = h->p.precision == RH_PREC_MIXED;
@@ -552,6 +602,139 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src) {
       launch_coarsen_faces<double, double>(h->stream, fd[0], fd[1], fd[2], f, h->L64[l]);
     }
     HIPCHK(hipGetLastError());
+  }
+  return plan_blocks(h, src);
+}
+
+// Two boxes (corners a, b; extents e) touch or overlap along an axis of n
+// cells when their distance is at most e (periodic axes: either way round).
+bool boxes_meet_1d(int a, int b, int e, int n, bool per) {
+  int d = std::abs(a - b);
+  if (per) d = std::min(d, n - d);
+  return d <= e;
+}
+
+// Boxes of the block smoother for this step: the source cells (src > 0),
+// on each level with boxes the coarse cells that contain them, one box of
+// radius R around each (shifted inwards so it never wraps), coloured
+// greedily in cell order so that boxes of one colour neither overlap nor
+// touch.  No boxes (this step) when there are no sources or more than
+// mg_block_max of them.
+rh_status plan_blocks(rh_handle* h, const double* src) {
+  h->nblk = 0;
+  const rh_params& p = h->p;
+  const int R = p.mg_block_radius;
+  const int blevels = R > 0 ? std::min(p.mg_block_levels, h->plan.nlev - 1) : 0;
+  h->nsrc = 0;
+  if (blevels == 0) return RH_OK;
+  const bool mixed = p.precision == RH_PREC_MIXED;
+  const int G = h->src_groups;
+  launch_src_count(h->stream, h->N, h->src_chunk, G, src, h->src_count);
+  HIPCHK(hipGetLastError());
+  std::vector<int> cnt(G), off(G);
+  HIPCHK(hipMemcpyAsync(cnt.data(), h->src_count, sizeof(int) * G, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  long long total = 0;
+  for (int g = 0; g < G; ++g) {
+    off[g] = (int)total;
+    total += cnt[g];
+  }
+  h->nsrc = (int)std::min<long long>(total, INT32_MAX);
+  if (total == 0 || total > block_capacity(p)) return RH_OK;
+  HIPCHK(hipMemcpyAsync(h->src_offset, off.data(), sizeof(int) * G, hipMemcpyHostToDevice, h->stream));
+  launch_src_list(h->stream, h->N, h->src_chunk, G, src, h->src_offset, h->src_list);
+  HIPCHK(hipGetLastError());
+  std::vector<int> cells((size_t)total);
+  HIPCHK(hipMemcpyAsync(cells.data(), h->src_list, sizeof(int) * total, hipMemcpyDeviceToHost,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int per[3] = {p.bc[0] == RH_BC_PERIODIC, p.bc[2] == RH_BC_PERIODIC, p.bc[4] == RH_BC_PERIODIC};
+  for (int l = 0; l < blevels; ++l) {
+    const int* n = h->plan.dims[l];
+    int e[3];
+    for (int a = 0; a < 3; ++a) e[a] = std::min(2 * R + 1, n[a]);
+    // coarse cells of the sources, unique, in cell order
+    std::vector<long long> cen;
+    cen.reserve(cells.size());
+    for (int c : cells) {
+      const long long i = c / ((long long)p.ny * p.nz), j = (c / p.nz) % p.ny, k = c % p.nz;
+      cen.push_back(((i >> l) * n[1] + (j >> l)) * n[2] + (k >> l));
+    }
+    std::sort(cen.begin(), cen.end());
+    cen.erase(std::unique(cen.begin(), cen.end()), cen.end());
+    const int nb = (int)cen.size();
+    std::vector<int> st(3 * (size_t)nb);
+    for (int b = 0; b < nb; ++b) {
+      const long long c[3] = {cen[b] / ((long long)n[1] * n[2]), (cen[b] / n[2]) % n[1],
+                              cen[b] % n[2]};
+      for (int a = 0; a < 3; ++a)
+        st[3 * b + a] = (int)std::min<long long>(std::max<long long>(c[a] - R, 0), n[a] - e[a]);
+    }
+    // greedy colouring through bins of width 2R + 2 (boxes in bins further
+    // apart along an axis cannot meet along it)
+    const int W = 2 * R + 2;
+    int nbin[3];
+    for (int a = 0; a < 3; ++a) nbin[a] = (n[a] + W - 1) / W;
+    std::vector<std::vector<int>> bins((size_t)nbin[0] * nbin[1] * nbin[2]);
+    std::vector<int> colour(nb, -1);
+    int ncol = 0;
+    for (int b = 0; b < nb; ++b) {
+      int bb[3];
+      for (int a = 0; a < 3; ++a) bb[a] = st[3 * b + a] / W;
+      unsigned long long used = 0;
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            int q[3] = {bb[0] + dx, bb[1] + dy, bb[2] + dz};
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+              if (q[a] < 0 || q[a] >= nbin[a]) {
+                if (!per[a]) ok = false;
+                q[a] = (q[a] + nbin[a]) % nbin[a];
+              }
+            }
+            if (!ok) continue;
+            for (int o : bins[((size_t)q[0] * nbin[1] + q[1]) * nbin[2] + q[2]]) {
+              bool meet = true;
+              for (int a = 0; a < 3; ++a)
+                meet = meet && boxes_meet_1d(st[3 * b + a], st[3 * o + a], e[a], n[a], per[a]);
+              if (meet && colour[o] < 64) used |= 1ull << colour[o];
+            }
+          }
+      int c = 0;
+      while (c < 64 && ((used >> c) & 1ull)) ++c;
+      if (c == 64) return fail(h, RH_EINVAL, "block smoother: more than 64 box colours");
+      colour[b] = c;
+      ncol = std::max(ncol, c + 1);
+      // the periodic wrap of the bins can map two neighbour offsets to one
+      // bin: each box is inserted once and tested against every box there
+      bins[((size_t)bb[0] * nbin[1] + bb[1]) * nbin[2] + bb[2]].push_back(b);
+    }
+    // boxes ordered by colour
+    std::vector<int> sorted(3 * (size_t)nb);
+    std::vector<int>& offc = h->bcolour[l];
+    offc.assign(ncol + 1, 0);
+    for (int b = 0; b < nb; ++b) ++offc[colour[b] + 1];
+    for (int c = 0; c < ncol; ++c) offc[c + 1] += offc[c];
+    std::vector<int> fill(offc.begin(), offc.end() - 1);
+    for (int b = 0; b < nb; ++b) {
+      const int dst = fill[colour[b]]++;
+      for (int a = 0; a < 3; ++a) sorted[3 * dst + a] = st[3 * b + a];
+    }
+    HIPCHK(hipMemcpyAsync(h->bstart[l], sorted.data(), sizeof(int) * 3 * nb, hipMemcpyHostToDevice,
+                          h->stream));
+    // the host vectors must outlive the copy
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (mixed) {
+      BlockSet<float>& B = h->B32[l];
+      B.n = nb; B.ex = e[0]; B.ey = e[1]; B.ez = e[2]; B.m = e[0] * e[1] * e[2];
+      B.start = h->bstart[l];
+    } else {
+      BlockSet<double>& B = h->B64[l];
+      B.n = nb; B.ex = e[0]; B.ey = e[1]; B.ez = e[2]; B.m = e[0] * e[1] * e[2];
+      B.start = h->bstart[l];
+    }
+    h->nblk = l + 1;
   }
   return RH_OK;
 }
@@ -627,6 +810,13 @@ template <>
 double* coarse_inverse<double>(rh_handle* h) { return h->cInv64; }
 
 template <class T>
+BlockSet<T>* block_sets(rh_handle* h);
+template <>
+BlockSet<float>* block_sets<float>(rh_handle* h) { return h->B32; }
+template <>
+BlockSet<double>* block_sets<double>(rh_handle* h) { return h->B64; }
+
+template <class T>
 rh_status coarse_setup(rh_handle* h) {
   LevelK<T>* L = levels<T>(h);
   phase_mark(h, PH_COARSE);
@@ -637,7 +827,29 @@ rh_status coarse_setup(rh_handle* h) {
                                coarse_inverse<T>(h));
   }
   HIPCHK(hipGetLastError());
+  // the block smoother's box inverses from this Newton iteration's operator
+  BlockSet<T>* B = block_sets<T>(h);
+  for (int l = 0; l < h->nblk; ++l) {
+    Timed tm(h, KK_BLOCKINV);
+    launch_block_inverse<T>(h->stream, L[l], B[l]);
+  }
+  HIPCHK(hipGetLastError());
   return RH_OK;
+}
+
+// Block relaxation on level l's boxes, colour by colour (forward before
+// coarsening, reversed after it: the cycle stays symmetric).
+template <class T>
+void block_relax(rh_handle* h, int l, bool forward) {
+  if (l >= h->nblk) return;
+  const BlockSet<T>& B = block_sets<T>(h)[l];
+  const std::vector<int>& off = h->bcolour[l];
+  const int nc = (int)off.size() - 1;
+  for (int i = 0; i < nc; ++i) {
+    const int c = forward ? i : nc - 1 - i;
+    Timed tm(h, l == 0 ? KK_BLOCK0 : KK_COARSE);
+    launch_block_relax<T>(h->stream, levels<T>(h)[l], B, off[c], off[c + 1] - off[c]);
+  }
 }
 
 // One red-black sweep on level l: fused (x -> x2, then swap) when the level
@@ -695,11 +907,15 @@ void vcycle(rh_handle* h, int l) {
     launch_coarsest_solve<T>(s, L[l], coarse_inverse<T>(h));
     return;
   }
-  // red first on the way down, black first on the way up: the cycle is symmetric
+  // red first on the way down, black first on the way up, and the source
+  // boxes after the pre-smoothing and before the post-smoothing: the cycle
+  // is symmetric
   for (int it = 0; it < h->p.mg_pre; ++it) sweep<T>(h, l, 0, it == 0);
+  block_relax<T>(h, l, true);
   residual_restrict<T>(h, l);
   vcycle<T>(h, l + 1);
   { Timed tm(h, l == 0 ? KK_PROLONG0 : KK_COARSE); launch_prolong<T>(s, L[l + 1], L[l]); }
+  block_relax<T>(h, l, false);
   for (int it = 0; it < h->p.mg_post; ++it) sweep<T>(h, l, 1, 0, it == h->p.mg_post - 1);
 }
 
@@ -974,6 +1190,9 @@ void rh_default_params(rh_params* p) {
   p->mg_coarse_max = 64;
   p->krylov = 1;
   p->smoother = 0;
+  p->mg_block_radius = 2;
+  p->mg_block_levels = 2;
+  p->mg_block_max = 0;
 }
 
 size_t rh_workspace_bytes(const rh_params* p) {
@@ -1155,6 +1374,7 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
     for (int q = 1; q <= 5; ++q) stats->t_ms[q] = h->pms[q];
     stats->lin_cap_hits = h->lin_cap_hits;
     stats->lin_its_max = h->lin_its_max;
+    stats->source_boxes = h->nblk > 0 ? h->B32[0].n + h->B64[0].n : 0;
   }
   return result;
 }

@@ -61,6 +61,21 @@ struct LevelK {
   T* cf[3];             // + face coefficients (dimensionless, 0 on a non-periodic last face)
 };
 
+// Source-centred boxes of one multigrid level for the block smoother
+// (rh_blocks.hip): n boxes of extent ex x ey x ez (m = ex ey ez cells,
+// at most kBlockMaxCells), each given by its lowest corner (3 ints, boxes
+// never wrap), ordered by colour; inv holds each box's inverse (m x m,
+// symmetric, so row and column order coincide).
+constexpr int kBlockMaxCells = 125;  // boxes of radius <= 2
+constexpr int kMaxBlockLevels = 4;
+template <class T>
+struct BlockSet {
+  int n;
+  int ex, ey, ez, m;
+  const int* start;
+  T* inv;
+};
+
 // Reduction slots (partials laid out [slot][kRedBlocks]).
 enum RedSlot {
   RS_FE2 = 0,      // sum (f_E/E_s)^2
@@ -224,6 +239,19 @@ void launch_pcg_update(hipStream_t s, const StepK& k, double alpha, const double
 template <class T>
 void launch_pcg_precond(hipStream_t s, const StepK& k, double sigma, const T* zT, const double* r,
                         const double* q, double* part);
+
+// block smoother (rh_blocks.hip)
+// count[g] = source cells (src > 0) among cells [g chunk, (g+1) chunk)
+void launch_src_count(hipStream_t s, long long N, long long chunk, int groups, const double* src,
+                      int* count);
+// list[offset[g] + rank] = the source cells of range g, in cell order
+void launch_src_list(hipStream_t s, long long N, long long chunk, int groups, const double* src,
+                     const int* offset, int* list);
+template <class T>
+void launch_block_inverse(hipStream_t s, const LevelK<T>& l, const BlockSet<T>& bs);
+// x += A_box^-1 (b - A x)_box on boxes [b0, b0 + nb) (one colour)
+template <class T>
+void launch_block_relax(hipStream_t s, const LevelK<T>& l, const BlockSet<T>& bs, int b0, int nb);
 
 // advection of the step's fields (operator split, step (iv)), rh_advect.hip
 struct AdvK {

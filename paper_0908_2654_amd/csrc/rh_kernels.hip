@@ -41,22 +41,6 @@ __device__ inline double outflow_sum(const StepK& k, int i, int j, int kk, doubl
   return s;
 }
 
-// Neighbour along axis d in direction s (+1/-1); returns false if none.
-__device__ inline bool neighbour(const int (&c)[3], const int (&n)[3], const int* per, int d,
-                                 int s, int (&q)[3]) {
-  q[0] = c[0]; q[1] = c[1]; q[2] = c[2];
-  int v = c[d] + s;
-  if (v < 0) {
-    if (!per[d]) return false;
-    v += n[d];
-  } else if (v >= n[d]) {
-    if (!per[d]) return false;
-    v -= n[d];
-  }
-  q[d] = v;
-  return true;
-}
-
 // ---------------------------------------------------------------------------
 // K0: per-step setup: + face coefficients, constant part of f_E, max E^n, max src
 // ---------------------------------------------------------------------------

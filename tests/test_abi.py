@@ -53,6 +53,8 @@ def _bytes(**over):
     ({"theta": 0.0}, "theta"), ({"theta": 1.5}, "theta"),
     ({"nx": 15}, "coarsened"), ({"krylov": 2}, "krylov"), ({"smoother": 3}, "smoother"),
     ({"cosmology": 4}, "cosmology"),
+    ({"mg_block_radius": 3}, "mg_block_radius"), ({"mg_block_levels": 5}, "mg_block_levels"),
+    ({"mg_block_max": -1}, "mg_block_max"),
     ({"cosmology": W.COSMO_EDS, "Omega_m": 0.3}, "EdS"),
     ({"cosmology": W.COSMO_OPEN, "Omega_m": 1.0}, "open"),
     ({"cosmology": W.COSMO_OPEN, "Omega_m": 0.1, "Omega_L": 0.2}, "open"),
@@ -65,12 +67,31 @@ def test_invalid_parameters_are_rejected_before_any_device_call(over, msg):
 
 
 def test_workspace_grows_with_the_grid():
-    n16, _ = _bytes()
-    n32, _ = _bytes(nx=32, ny=32, nz=32)
-    n32m, _ = _bytes(nx=32, ny=32, nz=32, precision=1)
+    n16, _ = _bytes(mg_block_radius=0)
+    n32, _ = _bytes(nx=32, ny=32, nz=32, mg_block_radius=0)
+    n32m, _ = _bytes(nx=32, ny=32, nz=32, precision=1, mg_block_radius=0)
     assert 0 < n16 < n32 and n16 < n32m
     # the FP64 fields alone; the mixed path keeps its hierarchy in FP32
     assert n32m > 8 * 20 * 32 ** 3 and n32 > n32m
+
+
+def test_workspace_of_the_source_boxes():
+    """Block smoother: per level with boxes, the inverses of up to
+    max(64, min(8192, N/4096)) boxes of (2R+1)^3 cells (FP64 or FP32) and
+    their corners, plus the source scan buffers."""
+    base, _ = _bytes(mg_block_radius=0)
+    for prec, T in ((0, 8), (1, 4)):
+        off, _ = _bytes(mg_block_radius=0, precision=prec)
+        on, _ = _bytes(precision=prec)                    # radius 2 on 2 levels, 64 boxes
+        inv = 2 * 64 * 125 * 125 * T
+        assert inv < on - off < inv + 64 * 1024
+    one, _ = _bytes(mg_block_levels=1)
+    r1, _ = _bytes(mg_block_radius=1)
+    assert one - base == pytest.approx(64 * 125 * 125 * 8, rel=0.01)
+    assert r1 - base == pytest.approx(2 * 64 * 27 * 27 * 8, abs=64 * 1024)
+    big, _ = _bytes(nx=512, ny=512, nz=512, precision=1)
+    big0, _ = _bytes(nx=512, ny=512, nz=512, precision=1, mg_block_radius=0)
+    assert big - big0 == pytest.approx(2 * 8192 * 125 * 125 * 4, rel=0.01)
 
 
 @pytest.mark.parametrize("kind,h,Om,OL", [(W.COSMO_EDS, 0.5, 1.0, 0.0),
