@@ -209,8 +209,8 @@ rh_status rh_implicit_step(rh_handle* h, double t_n_s, double dt_s, const double
  * Newton system; after local elimination the same symmetric Schur operator
  * as the forward step) and return lambda^n = -(df/dU^n)^T mu in (lE, le,
  * lnHI) (overwritten), and accumulate g_src += -(df/dsrc)^T mu and
- * g_nH += -(df/dnH)^T mu.  The transposed solve runs to ||r||_2 <= 1e-13 of
- * its right-hand side; if it stops short (lin_max_it reached, stagnation)
+ * g_nH += -(df/dnH)^T mu.  The transposed solve runs to ||r||_2 <= lin_forcing
+ * (default 1e-13) of its right-hand side; if it stops short (lin_max_it reached, stagnation)
  * the call returns RH_ELINEAR and leaves lE, le, lnHI, g_src, g_nH as they
  * were.  E_n..nHI_n and E_1..nHI_1 are the checkpoints
  * U^n and U^{n+1} (read only).  le and the e-checkpoints are ignored for

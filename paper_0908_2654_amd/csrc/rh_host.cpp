@@ -1668,8 +1668,8 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
   int its = 0;
   double w = 0, l2 = 0;
   bool reached = true;
-  st = solve_linear(h, k, rmax, 0.0, 1e-13 * rnorm, h->p.lin_max_it, &mu, &its, &w, &l2,
-                    &reached);
+  st = solve_linear(h, k, rmax, 0.0, h->p.lin_forcing * rnorm, h->p.lin_max_it, &mu, &its, &w,
+                    &l2, &reached);
   if (st != RH_OK) return st;
   h->lin_its = its;
   if (!reached) {
@@ -1690,7 +1690,8 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
     char buf[200];
     std::snprintf(buf, sizeof buf,
                   "adjoint linear solve stopped after %d cycles at relative residual %.3e "
-                  "(target 1e-13; raise lin_max_it)", its, rnorm > 0 ? l2 / rnorm : 0.0);
+                  "(target lin_forcing = %.1e; raise lin_max_it)", its,
+                  rnorm > 0 ? l2 / rnorm : 0.0, h->p.lin_forcing);
     return fail(h, RH_ELINEAR, buf);
   }
   phase_mark(h, PH_EVAL);
