@@ -399,6 +399,121 @@ const char* rh_last_error(const rh_handle* h);
 /* Release the handle (not the caller's workspace).  NULL is accepted. */
 void rh_destroy(rh_handle* h);
 
+/* ---- Hydrogen + helium chemistry with multigroup radiation -------------
+ * The extension the Conclusions and outlook section names first: the
+ * multi-frequency radiation equation (equation cons_radiation_multifreq)
+ * integrated over G frequency groups instead of one, and helium ionisation
+ * (electron density with helium: equation electron_density, second
+ * branch).  The paper prints neither; these are this library's definitions.
+ *
+ *  - Groups: lower edges edge_eV[0] = p->hnu0_eV < edge_eV[1] < ... (the
+ *    last group extends to infinity).  Within a group the spectrum keeps the
+ *    shape of the T_bb_K blackbody (equation grey_definition applied per
+ *    group).  With x = h nu / (k T_bb) and b(x) = 1 / (e^x - 1):
+ *      I_g = int_g x^3 b dx (group energy), f_g = I_g / sum_h I_h (share of
+ *      the source energy), and per species s = HI, HeI, HeII, with
+ *      sigma_s(nu) = sigma_s0 (nu_s / nu)^sigma_power above its threshold
+ *      nu_s (HI: hnu0_eV, sigma0_cm2; HeI: 24.587 eV, 7.42e-18 cm^2; HeII:
+ *      4 hnu0_eV, sigma0_cm2 / 4):
+ *        sigma_E[s][g] = int_g sigma_s x^3 b dx / I_g              (opacity)
+ *        K_Gamma[s][g] = int_g sigma_s x^2 b dx / (k T_bb I_g)      (ionisation)
+ *        K_G[s][g]     = sigma_E[s][g] - h nu_s K_Gamma[s][g]       (heating)
+ *    by host quadrature.  One group without helium gives the grey constants.
+ *  - Fields (device FP64, z fastest as above): E [G][N] (group energies,
+ *    group after group, erg cm^-3), e [N], y [3][N] = (n_HI, n_HeI, n_HeII)
+ *    (cm^-3, comoving); n_He = y_he n_H, n_HII = n_H - n_HI,
+ *    n_HeIII = n_He - n_HeI - n_HeII, n_e = n_HII + n_HeII + 2 n_HeIII,
+ *    mu = (n_H + 4 n_He) / (n_H + n_He + n_e), T = (gamma - 1) mu m_H e / k_B.
+ *    Without helium rows 1 and 2 of y are neither read nor written.
+ *  - Chemistry (equation chemical_ionization for each species):
+ *      dn_HI/dt   = alpha_H n_e n_HII - Gamma_HI n_HI
+ *      dn_HeI/dt  = alpha_HeII n_e n_HeII - Gamma_HeI n_HeI
+ *      dn_HeII/dt = Gamma_HeI n_HeI - (Gamma_HeII + alpha_HeII n_e) n_HeII
+ *                   + alpha_HeIII n_e n_HeIII
+ *    with Gamma_s = c sum_g K_Gamma[s][g] E_g (proper), alpha_H the grey
+ *    step's recombination rate, alpha_HeII = 1.26e-14 (570670 K / T)^0.75
+ *    cm^3 s^-1, alpha_HeIII(T) = 2 alpha_H(T / 4).
+ *  - Gas energy: heating c sum_s sum_g K_G[s][g] n_s E_g; the grey step's
+ *    cooling terms with the full n_e (recombination cooling n_e n_HII) and,
+ *    with RH_COOL_RECB, helium recombination cooling
+ *    k_B T alpha_HeII n_e n_HeII + 8 L_recB(T / 4) n_e n_HeIII.
+ *  - Discretisation: the grey step's, per group (opacity sum_s sigma_E[s][g]
+ *    n_s, face limiter from E_g^n and that opacity at t_n, source f_g src,
+ *    no exchange between groups) and per species (theta method with a and
+ *    M frozen at the implicit level:
+ *    (I + theta dt M(U)) S = y^n + dt [theta a(U) + (1 - theta)(a^n - M^n y^n)]).
+ *  - Norm: RMS over G + 4 unknowns per cell (one fewer when isothermal, two
+ *    fewer without helium), weights E_s of each group (as the grey E_s),
+ *    e^n, n_H for n_HI and n_He for the helium species.
+ * Solver: Newton with the local unknowns eliminated per cell.  The Schur
+ * system couples the groups only within a cell; it is solved by block
+ * Gauss-Seidel over the groups (at most lin_max_it sweeps), each group's
+ * 7-point system by the configured multigrid solve to 1/50 of its current
+ * residual, until the coupled residual is below lin_forcing ||f||.
+ * Isothermal runs accept e == NULL. */
+#define RH_MAX_GROUPS 4
+typedef struct rh_multigroup_params {
+  int32_t groups;                /* 1 .. RH_MAX_GROUPS                                  */
+  int32_t reserved;              /* 0                                                   */
+  double edge_eV[RH_MAX_GROUPS]; /* lower group edges, increasing, edge_eV[0] = hnu0_eV */
+  double y_he;                   /* n_He / n_H (0: hydrogen only)                       */
+  double sigma_power;            /* power of the cross-sections' frequency law (3)      */
+} rh_multigroup_params;
+
+typedef struct rh_multigroup rh_multigroup;
+
+/* Group constants for p (p->spectrum must be RH_SPEC_BLACKBODY) and mg,
+ * host only: out[0 .. G) f_g; then sigma_E, K_Gamma and K_G, each [3][G]
+ * (species HI, HeI, HeII; cm^2, cm^2 erg^-1, cm^2); then eps_bar (erg, mean
+ * photon energy of the whole spectrum above hnu0, as in the grey case).
+ * n >= 10 G + 1, else RH_EINVAL.  Errors: rh_last_error(NULL). */
+rh_status rh_multigroup_constants(const rh_params* p, const rh_multigroup_params* mg, double* out,
+                                  int32_t n);
+
+/* Bytes of device workspace rh_multigroup_setup needs (one grey workspace
+ * per group plus the coupled fields), or 0 if p or mg is invalid. */
+size_t rh_multigroup_workspace_bytes(const rh_params* p, const rh_multigroup_params* mg);
+
+/* As rh_setup, for the multigroup step: validates p (as rh_setup does) and
+ * mg, computes the group constants and carves the caller's workspace (at
+ * least rh_multigroup_workspace_bytes).  Errors: rh_last_error(NULL). */
+rh_status rh_multigroup_setup(const rh_params* p, const rh_multigroup_params* mg, void* workspace,
+                              size_t ws_bytes, void* hip_stream, rh_multigroup** out);
+
+/* Initial fields: E_g = f_g E0, n_HI = (1 - x0) n_H, n_HeI = (1 - x0) n_He,
+ * n_HeII = x0 n_He, and (e not NULL) e of temperature T0_K (T_iso_K when
+ * isothermal) at those fractions.  Arguments and errors as rh_initial_state. */
+rh_status rh_multigroup_initial_state(rh_multigroup* h, const double* nH, double x0, double T0_K,
+                                      double E0, double* E, double* e, double* y);
+
+/* One implicit step from t_n to t_n + dt_s of the multigroup system: In:
+ * E, e, y hold U^n; out: U^{n+1}.  On RH_ENEWTON, RH_ELINEAR or
+ * RH_ENONFINITE they are restored to U^n.  stats (may be NULL) as for
+ * rh_implicit_step, except lin_its_total (multigrid iterations over all
+ * groups and sweeps), lin_its_max (most block Gauss-Seidel sweeps of one
+ * Newton iteration) and lin_cap_hits (Newton iterations whose coupled solve
+ * stopped above its target); t_ms[1..5] are 0. */
+rh_status rh_multigroup_step(rh_multigroup* h, double t_n_s, double dt_s, const double* nH,
+                             const double* src, double* E, double* e, double* y,
+                             rh_step_stats* stats);
+
+/* Residual of the multigroup step from U^n = (E_n, e_n, y_n) at U = (E, e,
+ * y), as rh_multigroup_step evaluates it: fE [G][N], fe [N], fy [3][N]
+ * (device, each may be NULL; fe unused when isothermal, fy rows 1-2 without
+ * helium) and *norm_out (host) = ||f(U)||. */
+rh_status rh_multigroup_residual(rh_multigroup* h, double t_n_s, double dt_s, const double* nH,
+                                 const double* src, const double* E_n, const double* e_n,
+                                 const double* y_n, const double* E, const double* e,
+                                 const double* y, double* fE, double* fe, double* fy,
+                                 double* norm_out);
+
+/* Message of the last failed call on h (NULL: of the last failed
+ * rh_multigroup_setup / _constants / _workspace_bytes on this thread). */
+const char* rh_multigroup_last_error(const rh_multigroup* h);
+
+/* Release the handle (not the caller's workspace).  NULL is accepted. */
+void rh_multigroup_destroy(rh_multigroup* h);
+
 #ifdef __cplusplus
 }
 #endif

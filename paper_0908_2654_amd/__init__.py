@@ -8,3 +8,4 @@ Importing the package loads librh.so and fails if it is not built.
 """
 from ._lib import RhError, RhParams, RhStepStats, default_params  # noqa: F401
 from .solver import Solver, cosmic_time, cosmology_at, params_from_workload, workspace_bytes  # noqa: F401
+from .solver import MultigroupSolver, multigroup_constants, multigroup_params  # noqa: F401

@@ -87,6 +87,19 @@ class RhAdvectStats(ctypes.Structure):
 # exported symbols and their signatures (name -> (restype, argtypes))
 _PP = ctypes.POINTER(RhParams)
 _SP = ctypes.POINTER(RhStepStats)
+MAX_GROUPS = 4
+
+
+class RhMultigroupParams(ctypes.Structure):
+    _fields_ = [
+        ("groups", _i32), ("reserved", _i32),
+        ("edge_eV", _f64 * MAX_GROUPS),
+        ("y_he", _f64), ("sigma_power", _f64),
+    ]
+
+
+_MP = ctypes.POINTER(RhMultigroupParams)
+
 SIGNATURES = {
     "rh_default_params": (None, [_PP]),
     "rh_workspace_bytes": (ctypes.c_size_t, [_PP]),
@@ -116,6 +129,15 @@ SIGNATURES = {
                                     _i32, _i32]),
     "rh_last_error": (ctypes.c_char_p, [_vp]),
     "rh_destroy": (None, [_vp]),
+    "rh_multigroup_constants": (_i32, [_PP, _MP, ctypes.POINTER(_f64), _i32]),
+    "rh_multigroup_workspace_bytes": (ctypes.c_size_t, [_PP, _MP]),
+    "rh_multigroup_setup": (_i32, [_PP, _MP, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "rh_multigroup_initial_state": (_i32, [_vp, _vp, _f64, _f64, _f64, _vp, _vp, _vp]),
+    "rh_multigroup_step": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _SP]),
+    "rh_multigroup_residual": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, ctypes.POINTER(_f64)]),
+    "rh_multigroup_last_error": (ctypes.c_char_p, [_vp]),
+    "rh_multigroup_destroy": (None, [_vp]),
 }
 
 
@@ -142,6 +164,12 @@ class RhError(RuntimeError):
 def check(status, handle=None):
     if status != RH_OK:
         msg = lib.rh_last_error(handle)
+        raise RhError(status, msg.decode() if msg else "")
+
+
+def check_multigroup(status, handle=None):
+    if status != RH_OK:
+        msg = lib.rh_multigroup_last_error(handle)
         raise RhError(status, msg.decode() if msg else "")
 
 

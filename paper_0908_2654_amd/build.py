@@ -11,6 +11,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["csrc/rh_kernels.hip", "csrc/rh_advect.hip", "csrc/rh_blocks.hip", "csrc/rh_noalloc.hip",
+           "csrc/rh_groups.hip",
            "csrc/rh_host.cpp"]
 LIB = os.path.join(PKG, "librh.so")
 ARCH = os.environ.get("RH_OFFLOAD_ARCH", "gfx950")

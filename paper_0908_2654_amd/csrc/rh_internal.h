@@ -45,6 +45,11 @@ struct StepK {
   double cf_scale;      // dt theta / (a_1^2 h^2): face D -> dimensionless coefficient
   double expl_ratio;    // (1-theta)/theta (a_1/a_n)^2: implicit -> explicit coefficient
   double E_s;           // norm scale of E
+  // multigroup: the group's cross-sections of HeI and HeII (sigma_E above is
+  // the hydrogen one; the opacity adds sig_he[0] n_HeI + sig_he[1] n_HeII
+  // where the helium fields are given) and its share of the source
+  double sig_he[2];
+  double src_frac;
 };
 
 // One multigrid level (T = float or double).
@@ -124,7 +129,9 @@ void launch_init_state(hipStream_t s, long long N, double E0, double keep, doubl
 // out = scale in; RS_NONFINITE flags a negative or non-finite input.
 void launch_scale_field(hipStream_t s, long long N, double scale, const double* in, double* out,
                         double* part);
+// y1n, y2n: n_HeI^n, n_HeII^n of a multigroup step (both null: hydrogen only).
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
+                       const double* y1n, const double* y2n,
                        const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
                        float* cf32_x, float* cf32_y, float* cf32_z, double* rhsn,
                        double* part);
@@ -149,6 +156,12 @@ struct ResidArgs {
   const double* cf[3]; const double* rhsn;
   const double* BCn; const double* Bfn;
   double* rS; double* diag64; float* diag32; double* fE_out;
+  // multigroup (all null for the grey step): helium densities of the state
+  // and of U^n, and the group's Schur terms from the local elimination
+  // (kB = sum_s J_gs (B^-1 f)_s, Kgg = sum_s J_gs (B^-1 C)_sg), which then
+  // replace the grey JEn Bfn and JEn BCn
+  const double* y1; const double* y2; const double* y1n; const double* y2n;
+  const double* kB; const double* Kgg;
 };
 void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* part);
 
@@ -252,6 +265,52 @@ void launch_block_inverse(hipStream_t s, const LevelK<T>& l, const BlockSet<T>& 
 // x += A_box^-1 (b - A x)_box on boxes [b0, b0 + nb) (one colour)
 template <class T>
 void launch_block_relax(hipStream_t s, const LevelK<T>& l, const BlockSet<T>& bs, int b0, int nb);
+
+// ---- hydrogen + helium chemistry with multigroup radiation (rh_groups.hip)
+// Local unknowns per cell, in this order: e, n_HI, n_HeI, n_HeII (an
+// isothermal run keeps e = 0 with a trivial equation; a run without helium
+// keeps the helium densities at 0 the same way).  Group fields are stored
+// group after group ([G][N]); species fields [3][N] (n_HI, n_HeI, n_HeII).
+constexpr int kMaxGroups = RH_MAX_GROUPS;
+constexpr int kLoc = 4;
+struct GroupK {
+  int G;                              // groups
+  int he;                             // helium present (y_he > 0)
+  double y_he;                        // n_He / n_H
+  double KGam[3][kMaxGroups];         // Gamma_s = c sum_g KGam[s][g] E_g (E proper)
+  double KG[3][kMaxGroups];           // heating c sum_s sum_g KG[s][g] n_s E_g
+  double sigE[3][kMaxGroups];         // opacity of group g: sum_s sigE[s][g] n_s
+};
+struct GroupLocalArgs {
+  const double* Ek; const double* dE; double lam;  // E_k [G][N]; trial E = E_k + lam dE
+  const double* ek; const double* yk;              // e [N] (null: isothermal), species [3][N]
+  const double* pBf; const double* pBC;            // predictor data of U_k (may be null)
+  const double* En; const double* en; const double* yn; const double* nH;
+  double* Et; double* et; double* yt;              // outputs (mode 0)
+  double* Bf;                                      // [4][N]  B^-1 f_loc
+  double* BC;                                      // [4][G][N]  B^-1 C
+  double* K;                                       // [G][G][N]  J B^-1 C
+  double* kB;                                      // [G][N]  J B^-1 f_loc
+  double* fe_out; double* fy_out;                  // optional residual outputs
+  int mode;                                        // 0: solve at E, 1: evaluate
+};
+// Local solve (mode 0) or evaluation (mode 1) with partial sums of
+// (f_e/e^n)^2 (RS_FE_LOC2), (f_HI/n_H)^2 + (f_HeI/n_He)^2 + (f_HeII/n_He)^2
+// (RS_FN2), failures, iterations and non-finite values.
+void launch_local_groups(hipStream_t s, const StepK& k, const GroupK& m, const GroupLocalArgs& a,
+                     double* part);
+// b = rS_g - S_gg x_g + sum_{h != g} K_gh x_h (the coupled Schur residual of
+// group g at x), with partial sums of (b/E_s)^2 (RS_FE2), b^2 (RS_R2) and
+// max |b| (RS_RMAX); diag and cf are group g's operator.
+void launch_group_coupled(hipStream_t s, const StepK& k, int G, int g, const double* rS,
+                       const double* diag, const double* const cf[3], const double* K,
+                       const double* x, double* b, double* part);
+// E_g = frac[g] E0, n_HI = (1 - x0) n_H, with helium n_HeI = (1 - x0) n_He
+// and n_HeII = x0 n_He, e = e0 (e null: isothermal); RS_NONFINITE flags a
+// bad n_H.
+void launch_groups_init(hipStream_t s, long long N, const GroupK& m, const double* frac, double E0,
+                    double x0, double e0, const double* nH, double* E, double* e, double* y,
+                    double* part);
 
 // advection of the step's fields (operator split, step (iv)), rh_advect.hip
 struct AdvK {

@@ -10,6 +10,7 @@
 #include <type_traits>
 
 #include "rh_device.h"
+#include "rh_dual.h"
 #include "rh_internal.h"
 
 namespace rh {
@@ -46,6 +47,7 @@ __device__ inline double outflow_sum(const StepK& k, int i, int j, int kk, doubl
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ nn,
+             const double* __restrict__ y1n, const double* __restrict__ y2n,
              const double* __restrict__ src, double* __restrict__ cfx, double* __restrict__ cfy,
              double* __restrict__ cfz, float* __restrict__ c32x, float* __restrict__ c32y,
              float* __restrict__ c32z, double* __restrict__ rhsn, double* __restrict__ part) {
@@ -53,6 +55,14 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
                       k.bc[4] == RH_BC_PERIODIC};
   const int n[3] = {k.nx, k.ny, k.nz};
   const double kfac = k.sigma_E / (k.a_n * k.a_n * k.a_n);
+  const double kf1 = k.sig_he[0] / (k.a_n * k.a_n * k.a_n);
+  const double kf2 = k.sig_he[1] / (k.a_n * k.a_n * k.a_n);
+  // opacity kappa^n of a cell (helium terms only in a multigroup step)
+  auto kap = [&](long long i) {
+    double v = kfac * nn[i];
+    if (y1n) v += kf1 * y1n[i] + kf2 * y2n[i];
+    return v;
+  };
   double emax = 0.0, smax = 0.0, bad = 0.0;
   double* cfo[3] = {cfx, cfy, cfz};
   float* c32[3] = {c32x, c32y, c32z};
@@ -63,8 +73,8 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
     int c[3];
     cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
     const double EP = En[idx];
-    const double kP = kfac * nn[idx];
-    const double sP = src[idx];
+    const double kP = kap(idx);
+    const double sP = k.src_frac * src[idx];
     emax = fmax(emax, EP);
     smax = fmax(smax, sP);
     if (!isfinite(EP) || !isfinite(sP) || !isfinite(kP)) bad = 1.0;
@@ -76,7 +86,7 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
       if (neighbour(c, n, per, d, +1, q)) {
         long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         double EQ = En[Q];
-        cfp = k.cf_scale * limiter_D(k, EP, EQ, kP, kfac * nn[Q]);
+        cfp = k.cf_scale * limiter_D(k, EP, EQ, kP, kap(Q));
         Ln += cfp * (EQ - EP);
       }
       cfo[d][idx] = cfp;
@@ -84,7 +94,7 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
       if (k.theta_lt1 && neighbour(c, n, per, d, -1, q)) {
         long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         double EQ = En[Q];
-        Ln += k.cf_scale * limiter_D(k, EQ, EP, kfac * nn[Q], kP) * (EQ - EP);
+        Ln += k.cf_scale * limiter_D(k, EQ, EP, kap(Q), kP) * (EQ - EP);
       }
     }
     double r = EP + k.dt * k.theta * sP;
@@ -104,10 +114,11 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
 }
 
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
-                       const double* src, double* cfx, double* cfy, double* cfz, float* c32x,
-                       float* c32y, float* c32z, double* rhsn, double* part) {
-  hipLaunchKernelGGL(k_step_setup, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, En, nn, src, cfx,
-                     cfy, cfz, c32x, c32y, c32z, rhsn, part);
+                       const double* y1n, const double* y2n, const double* src, double* cfx,
+                       double* cfy, double* cfz, float* c32x, float* c32y, float* c32z,
+                       double* rhsn, double* part) {
+  hipLaunchKernelGGL(k_step_setup, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, En, nn, y1n, y2n,
+                     src, cfx, cfy, cfz, c32x, c32y, c32z, rhsn, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -168,143 +179,14 @@ __device__ inline D3 dlog(D3 a) {
   return D3{log(a.v), {a.g[0] * iv, a.g[1] * iv, a.g[2] * iv}};
 }
 __device__ inline D3 dmax0(D3 a) { return a.v >= 0.0 ? a : dconst(0.0); }
-__device__ inline double dexp(double a) { return exp(a); }
-__device__ inline double dpow(double a, double p) { return pow(a, p); }
-__device__ inline double dsqrt(double a) { return sqrt(a); }
-__device__ inline double dlog(double a) { return log(a); }
-__device__ inline double dmax0(double a) { return fmax(a, 0.0); }
-template <class S>
-__device__ inline S lift(double v);
-template <>
-__device__ inline double lift<double>(double v) { return v; }
 template <>
 __device__ inline D3 lift<D3>(double v) { return dconst(v); }
 
-// Forward-mode dual numbers with NV derivative slots (the local solve uses
-// two, the adjoint's local terms seven).
-template <int NV>
-struct DN {
-  double v, g[NV];
-};
-template <int NV>
-__device__ inline DN<NV> dn_const(double v) {
-  DN<NV> r;
-  r.v = v;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = 0.0;
-  return r;
-}
-template <int NV>
-__device__ inline DN<NV> dn_var(double v, int slot) {
-  DN<NV> r = dn_const<NV>(v);
-  r.g[slot] = 1.0;
-  return r;
-}
-#define RH_DN_BIN(OP, VAL, GRAD)                                                   \
-  template <int NV>                                                                \
-  __device__ inline DN<NV> operator OP(DN<NV> a, DN<NV> b) {                       \
-    DN<NV> r;                                                                      \
-    r.v = VAL;                                                                     \
-    _Pragma("unroll") for (int i = 0; i < NV; ++i) r.g[i] = GRAD;                  \
-    return r;                                                                      \
-  }
-RH_DN_BIN(+, a.v + b.v, a.g[i] + b.g[i])
-RH_DN_BIN(-, a.v - b.v, a.g[i] - b.g[i])
-RH_DN_BIN(*, a.v * b.v, a.g[i] * b.v + a.v * b.g[i])
-#undef RH_DN_BIN
-template <int NV>
-__device__ inline DN<NV> operator/(DN<NV> a, DN<NV> b) {
-  const double iv = 1.0 / b.v, q = a.v * iv;
-  DN<NV> r;
-  r.v = q;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = (a.g[i] - q * b.g[i]) * iv;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> operator+(DN<NV> a, double b) { return a + dn_const<NV>(b); }
-template <int NV> __device__ inline DN<NV> operator+(double b, DN<NV> a) { return dn_const<NV>(b) + a; }
-template <int NV> __device__ inline DN<NV> operator-(DN<NV> a, double b) { return a - dn_const<NV>(b); }
-template <int NV> __device__ inline DN<NV> operator-(double b, DN<NV> a) { return dn_const<NV>(b) - a; }
-template <int NV>
-__device__ inline DN<NV> operator*(DN<NV> a, double b) {
-  DN<NV> r;
-  r.v = a.v * b;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * b;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> operator*(double b, DN<NV> a) { return a * b; }
-template <int NV> __device__ inline DN<NV> operator/(DN<NV> a, double b) { return a * (1.0 / b); }
-template <int NV> __device__ inline DN<NV> operator/(double b, DN<NV> a) { return dn_const<NV>(b) / a; }
-template <int NV>
-__device__ inline DN<NV> chain(DN<NV> a, double fv, double dfv) {
-  DN<NV> r;
-  r.v = fv;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) r.g[i] = a.g[i] * dfv;
-  return r;
-}
-template <int NV> __device__ inline DN<NV> dexp(DN<NV> a) { const double e = exp(a.v); return chain(a, e, e); }
-template <int NV> __device__ inline DN<NV> dpow(DN<NV> a, double p) { const double pv = pow(a.v, p); return chain(a, pv, p * pv / a.v); }
-template <int NV> __device__ inline DN<NV> dsqrt(DN<NV> a) { const double s = sqrt(a.v); return chain(a, s, 0.5 / s); }
-template <int NV> __device__ inline DN<NV> dlog(DN<NV> a) { return chain(a, log(a.v), 1.0 / a.v); }
-template <int NV> __device__ inline DN<NV> dmax0(DN<NV> a) { return a.v >= 0.0 ? a : dn_const<NV>(0.0); }
-template <int NV> __device__ inline DN<NV> dfabs(DN<NV> a) { return a.v < 0.0 ? dn_const<NV>(0.0) - a : a; }
-template <int NV> __device__ inline DN<NV> dfmax(DN<NV> a, double c) { return a.v >= c ? a : dn_const<NV>(c); }
-template <>
-__device__ inline DN<7> lift<DN<7>>(double v) { return dn_const<7>(v); }
-template <>
-__device__ inline DN<2> lift<DN<2>>(double v) { return dn_const<2>(v); }
-
-// Rate fits (Hui & Gnedin 1997 case B; Cen 1992 collisional excitation).
-// The case-B fits are powers of lambda = 315614 K / T and of 1 + (lambda /
-// c)^p; they are evaluated as exponentials of L = ln(lambda), which the
-// recombination rate and the recombination cooling share: 3 logarithms and
-// 4 exponentials instead of 6 general powers (the ALU-bound local solve
-// evaluates them in every iteration).
-constexpr double kLn315614 = 12.662275226919286;  // ln(315614)
-constexpr double kLn2p740 = 1.0079579203999789;   // ln(2.740)
-constexpr double kLn2p250 = 0.8109302162163288;   // ln(2.250)
-template <class S>
-__device__ inline S hg_ln_lambda(S T) {
-  return kLn315614 - dlog(T);
-}
-template <class S>
-__device__ inline S alpha_B_of_L(S L) {
-  S den = 1.0 + dexp(0.407 * (L - kLn2p740));
-  return 2.753e-14 * dexp(1.5 * L - 2.242 * dlog(den));
-}
-template <class S>
-__device__ inline S cool_recB_of_L(S T, S L) {
-  S den = 1.0 + dexp(0.376 * (L - kLn2p250));
-  return 3.435e-30 * T * dexp(1.970 * L - 3.720 * dlog(den));
-}
-template <class S>
-__device__ inline S alpha_B_fit(S T) {
-  return alpha_B_of_L(hg_ln_lambda(T));
-}
-template <class S>
-__device__ inline S cool_recB(S T) {
-  return cool_recB_of_L(T, hg_ln_lambda(T));
-}
-template <class S>
-__device__ inline S cool_collexc(S T) {
-  return 7.5e-19 * dexp(-118348.0 / T) / (1.0 + dsqrt(T / 1.0e5));
-}
-
 // The temperature fits are functions of T alone: evaluate them once with one
 // derivative slot (d/dT) and chain the result into the caller's dual numbers.
-__device__ inline double dval(double a) { return a; }
 __device__ inline double dval(const D3& a) { return a.v; }
-template <int NV>
-__device__ inline double dval(const DN<NV>& a) { return a.v; }
-__device__ inline double dchain(double, double fv, double) { return fv; }
 __device__ inline D3 dchain(const D3& x, double fv, double dfv) {
   return D3{fv, {x.g[0] * dfv, x.g[1] * dfv, x.g[2] * dfv}};
-}
-template <int NV>
-__device__ inline DN<NV> dchain(const DN<NV>& x, double fv, double dfv) {
-  return chain(x, fv, dfv);
 }
 struct TFits {
   double alpha, dalpha, recB, drecB, ce, dce;  // values and d/dT
@@ -548,12 +430,24 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
     bool bnd = (c[0] == 0 || c[0] == k.nx - 1 || c[1] == 0 || c[1] == k.ny - 1 || c[2] == 0 ||
                 c[2] == k.nz - 1);
     double bs = 0.0;
-    if (bnd) bs = outflow_sum(k, c[0], c[1], c[2], a.En[idx], kfac_n * a.nn[idx]);
-    const double absorb = kC * k.sigma_E * nP / a13;
+    if (bnd) {
+      double kn = kfac_n * a.nn[idx];
+      if (a.y1n) kn += (k.sig_he[0] * a.y1n[idx] + k.sig_he[1] * a.y2n[idx]) / (k.a_n * k.a_n * k.a_n);
+      bs = outflow_sum(k, c[0], c[1], c[2], a.En[idx], kn);
+    }
+    double absorb = kC * k.sigma_E * nP / a13;
+    if (a.y1) absorb += kC * (k.sig_he[0] * a.y1[idx] + k.sig_he[1] * a.y2[idx]) / a13;
     const double fE = EP + dth * (k.H_1 + absorb) * EP - LE + bs * (EP - k.E_floor) - a.rhsn[idx];
-    const double JEn = dth * kC * k.sigma_E * EP / a13;
-    const double diag = 1.0 + dth * (k.H_1 + absorb) + csum + bs - JEn * a.BCn[idx];
-    const double rS = -fE + JEn * a.Bfn[idx];
+    double diag = 1.0 + dth * (k.H_1 + absorb) + csum + bs;
+    double rS = -fE;
+    if (a.kB) {
+      diag -= a.Kgg[idx];
+      rS += a.kB[idx];
+    } else {
+      const double JEn = dth * kC * k.sigma_E * EP / a13;
+      diag -= JEn * a.BCn[idx];
+      rS += JEn * a.Bfn[idx];
+    }
     if (a.rS) a.rS[idx] = rS;
     if (a.diag64) a.diag64[idx] = diag;
     if (a.diag32) a.diag32[idx] = (float)diag;

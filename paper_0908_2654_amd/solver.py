@@ -257,3 +257,110 @@ class Solver:
                                 _ptr(le), _ptr(ln), _ptr(g_src), _ptr(g_nH), ctypes.byref(st))
         check(s, self._h)
         return st.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# hydrogen + helium chemistry with multigroup radiation
+# ---------------------------------------------------------------------------
+def multigroup_params(edges_eV, y_he=0.0, sigma_power=3.0) -> _lib.RhMultigroupParams:
+    """The C struct for lower group edges edges_eV (first = the hydrogen
+    threshold), helium abundance n_He / n_H and the cross-sections' power law."""
+    if not 1 <= len(edges_eV) <= _lib.MAX_GROUPS:
+        raise ValueError(f"1 to {_lib.MAX_GROUPS} groups")
+    m = _lib.RhMultigroupParams()
+    m.groups = len(edges_eV)
+    for i, v in enumerate(edges_eV):
+        m.edge_eV[i] = float(v)
+    m.y_he = float(y_he)
+    m.sigma_power = float(sigma_power)
+    return m
+
+
+def multigroup_constants(p: RhParams, mg) -> dict:
+    """Group constants (host): frac [G], sigma_E, K_Gamma, K_G [3][G] (HI,
+    HeI, HeII) and eps_bar."""
+    G = mg.groups
+    n = 10 * G + 1
+    out = (_F64 * n)()
+    _lib.check_multigroup(lib.rh_multigroup_constants(ctypes.byref(p), ctypes.byref(mg), out, n))
+    v = list(out)
+    rows = lambda o: [v[o + s * G: o + (s + 1) * G] for s in range(3)]  # noqa: E731
+    return {"frac": v[:G], "sigma_E": rows(G), "K_Gamma": rows(4 * G), "K_G": rows(7 * G),
+            "eps_bar": v[10 * G]}
+
+
+class MultigroupSolver:
+    """Handle of the multigroup step on one device/stream.  Fields: E [G, *dims],
+    e [*dims], y [3, *dims] (n_HI, n_HeI, n_HeII), float64, contiguous."""
+
+    def __init__(self, params: RhParams, mg, device="cuda", stream=None):
+        self.params = params
+        self.mg = mg
+        self.G = mg.groups
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a HIP device")
+        torch.cuda.init()
+        if self.device.index is not None:
+            torch.cuda.set_device(self.device)
+        else:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        nb = lib.rh_multigroup_workspace_bytes(ctypes.byref(params), ctypes.byref(mg))
+        if nb == 0:
+            _lib.check_multigroup(_lib.RH_EINVAL)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = ctypes.c_void_p()
+        st = lib.rh_multigroup_setup(ctypes.byref(params), ctypes.byref(mg),
+                                     ctypes.c_void_p(self.ws.data_ptr()), nb,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _lib.check_multigroup(st)
+        self._h = h
+
+    @property
+    def dims(self):
+        p = self.params
+        return (p.nx, p.ny, p.nz)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.rh_multigroup_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_state(self):
+        """Uninitialised (E, e, y) of the right shapes on the device."""
+        o = dict(dtype=torch.float64, device=self.device)
+        e = None if self.params.isothermal else torch.empty(self.dims, **o)
+        return torch.empty((self.G,) + self.dims, **o), e, torch.zeros((3,) + self.dims, **o)
+
+    def initial_state(self, nH, x0, T0, E0, E, e, y):
+        s = lib.rh_multigroup_initial_state(self._h, _ptr(nH), float(x0), float(T0), float(E0),
+                                            _ptr(E), _ptr(e), _ptr(y))
+        _lib.check_multigroup(s, self._h)
+
+    def step(self, t, dt, nH, src, E, e, y) -> dict:
+        st = RhStepStats()
+        s = lib.rh_multigroup_step(self._h, float(t), float(dt), _ptr(nH), _ptr(src), _ptr(E),
+                                   _ptr(e), _ptr(y), ctypes.byref(st))
+        _lib.check_multigroup(s, self._h)
+        return st.as_dict()
+
+    def residual(self, t, dt, nH, src, Un, U):
+        """f(U) of the step from U^n = (E, e, y): returns (fE, fe, fy, norm)."""
+        En, en, yn = Un
+        E, e, y = U
+        fE = torch.empty_like(E)
+        fe = None if self.params.isothermal else torch.empty_like(e)
+        fy = torch.zeros_like(y)
+        norm = _F64()
+        s = lib.rh_multigroup_residual(self._h, float(t), float(dt), _ptr(nH), _ptr(src),
+                                       _ptr(En), _ptr(en), _ptr(yn), _ptr(E), _ptr(e), _ptr(y),
+                                       _ptr(fE), _ptr(fe), _ptr(fy), ctypes.byref(norm))
+        _lib.check_multigroup(s, self._h)
+        return fE, fe, fy, norm.value

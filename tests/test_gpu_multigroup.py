@@ -1,0 +1,244 @@
+"""GPU parity of the hydrogen + helium multigroup step (rh_multigroup_*)
+against the multigroup oracle (oracle/multigroup.py) on the same seeded
+inputs: initial fields, residuals at perturbed states (elementwise), whole
+steps in FP64 and mixed precision (elementwise), and the one-group,
+hydrogen-only limit against the grey GPU step."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import cached, elementwise, to_dev
+from oracle import model as OM, multigroup as MG
+
+pytestmark = pytest.mark.gpu
+
+EDGES3 = (13.6, 24.587, 54.4)
+EDGES4 = (13.6, 20.0, 30.0, 60.0)
+
+# name -> (workload id, dims, Workload overrides, edges, y_he, steps)
+MG_CASES = {
+    "he3_lognormal": (2, (8, 8, 16), {"n_sources": 3}, EDGES3, 0.08, 2),
+    "he4_eds": (1, (8, 8, 8), {}, EDGES4, 0.08, 2),
+    "he3_theta06": (2, (8, 8, 8), {"theta": 0.6, "dt_Myr": 0.02, "n_sources": 2}, EDGES3, 0.08, 2),
+    "he2_iso": (1, (8, 8, 8), {"isothermal": True}, EDGES3[:2], 0.08, 2),
+    "he3_lcdm": (4, (8, 8, 8), {"n_sources": 4}, EDGES3, 0.08, 1),
+    "h3_nohe": (2, (8, 8, 8), {"n_sources": 2}, EDGES3, 0.0, 2),
+    # several workgroups and ragged sizes (residual only: the oracle's
+    # direct solve would be slow here)
+    "he3_ragged": (2, (24, 20, 36), {}, EDGES3, 0.08, 0),
+}
+
+
+def _setup(name, **pover):
+    cfg, dims, over, edges, y_he, nsteps = MG_CASES[name]
+    w = W.scaled(cfg, dims)
+    for k, v in over.items():
+        setattr(w, k, v)
+    mp = MG.params_from_workload(w, edges, y_he, **pover)
+    nH = W.density_field(w)
+    src = OM.source_field(mp.base, W.photon_rate_field(w))
+    t0, dt, _ = OM.schedule(mp.base, w)
+    E, e, y = MG.initial_state(mp, nH, w.x0, w.T0, w.E0)
+    return w, mp, dict(nH=nH, src=src, E=E, e=e, y=y, t0=t0, dt=dt, nsteps=nsteps)
+
+
+def _solver(w, mp, dev, **prm):
+    import paper_0908_2654_amd as P
+    p = P.params_from_workload(w, **prm)
+    m = P.multigroup_params(mp.edges_eV, mp.y_he, mp.sigma_power)
+    return P.MultigroupSolver(p, m, device=dev)
+
+
+def _gpu_state(inp, dev, iso):
+    return (to_dev(inp["E"], dev), None if iso else to_dev(inp["e"], dev), to_dev(inp["y"], dev))
+
+
+def test_initial_fields_match_oracle(hip_device):
+    for name in ("he3_lognormal", "he2_iso", "h3_nohe"):
+        w, mp, inp = _setup(name)
+        s = _solver(w, mp, hip_device)
+        E, e, y = s.empty_state()
+        s.initial_state(to_dev(inp["nH"], hip_device), w.x0, w.T0, w.E0, E, e, y)
+        assert elementwise(E.cpu().numpy(), inp["E"], 1e-30) < 1e-15, name
+        nrows = 3 if mp.he else 1
+        assert elementwise(y.cpu().numpy()[:nrows], inp["y"][:nrows], 1e-30) < 1e-15, name
+        if e is not None:
+            assert elementwise(e.cpu().numpy(), inp["e"], 1e-30) < 1e-14, name
+        s.close()
+
+
+def _perturbed(name, mp, inp):
+    """U^n one oracle step on; U = U^n perturbed within the admissible set."""
+    En, en, yn = cached(("mg_first", name), lambda: MG.step(
+        mp, inp["t0"], inp["dt"], inp["nH"], inp["src"], inp["E"], inp["e"], inp["y"], tol=1e-10))
+    rng = np.random.default_rng(7)
+    E = En * (1 + 0.2 * rng.standard_normal(En.shape)) + 1e-3 * En.max() * rng.random(En.shape)
+    nHe = mp.y_he * inp["nH"]
+    y = yn.copy()
+    y[0] = np.clip(yn[0] * (1 + 0.1 * rng.standard_normal(yn[0].shape)), 0, inp["nH"])
+    if mp.he:
+        y[1] = np.clip(yn[1] * (1 + 0.1 * rng.standard_normal(yn[1].shape)), 0, nHe)
+        y[2] = np.clip(yn[2] * (1 + 0.1 * rng.standard_normal(yn[2].shape)), 0, nHe - y[1])
+    e = en * (1 + 0.1 * rng.random(en.shape))
+    return (En, en, yn), (E, e, y)
+
+
+@pytest.mark.parametrize("name", list(MG_CASES))
+def test_residual_parity(hip_device, name):
+    w, mp, inp = _setup(name)
+    if MG_CASES[name][5] == 0:
+        # large case: U^n from the initial state perturbed instead of a step
+        rng = np.random.default_rng(3)
+        Un = (inp["E"] * (1 + 0.3 * rng.random(inp["E"].shape)), inp["e"], inp["y"])
+        _, U = _perturbed_from(mp, inp, Un, rng)
+    else:
+        Un, U = _perturbed(name, mp, inp)
+    t, dt = inp["t0"] + inp["dt"], inp["dt"]
+    ctx = MG.make_context(mp, t, dt, inp["nH"], inp["src"], *Un)
+    fE, fe, fy = MG.residual(mp, ctx, U[0], None if mp.base.isothermal else U[1], U[2])
+    nrm = MG.norm(mp, ctx, fE, fe, fy)
+    s = _solver(w, mp, hip_device)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    iso = mp.base.isothermal
+    Ung = (d(Un[0]), None if iso else d(Un[1]), d(Un[2]))
+    Ug = (d(U[0]), None if iso else d(U[1]), d(U[2]))
+    gE, ge, gy, gnorm = s.residual(t, dt, d(inp["nH"]), d(inp["src"]), Ung, Ug)
+    s.close()
+    gE, gy = gE.cpu().numpy(), gy.cpu().numpy()
+    errs = {f"fE{g}": elementwise(gE[g], fE[g], 1e-12) for g in range(mp.G)}
+    errs["fHI"] = elementwise(gy[0], fy[0], 1e-12)
+    if mp.he:
+        errs["fHeI"] = elementwise(gy[1], fy[1], 1e-12)
+        errs["fHeII"] = elementwise(gy[2], fy[2], 1e-12)
+    if not iso:
+        errs["fe"] = elementwise(ge.cpu().numpy(), fe, 1e-12)
+    print(name, {k: f"{v:.1e}" for k, v in errs.items()}, gnorm, nrm)
+    assert max(errs.values()) < 1e-11
+    assert gnorm == pytest.approx(nrm, rel=1e-12)
+
+
+def _perturbed_from(mp, inp, Un, rng):
+    En, en, yn = Un
+    E = En * (1 + 0.2 * rng.standard_normal(En.shape)) + 1e-3 * En.max() * rng.random(En.shape)
+    nHe = mp.y_he * inp["nH"]
+    y = yn.copy()
+    y[0] = np.clip(inp["nH"] * rng.random(yn[0].shape), 0, inp["nH"])
+    if mp.he:
+        y[1] = nHe * 0.6 * rng.random(yn[1].shape)
+        y[2] = (nHe - y[1]) * rng.random(yn[2].shape)
+    e = en * (1 + 0.5 * rng.random(en.shape))
+    return Un, (E, e, y)
+
+
+def _oracle_traj(name, mp, inp, tol):
+    def run():
+        E, e, y = inp["E"], inp["e"], inp["y"]
+        for k in range(inp["nsteps"]):
+            E, e, y = MG.step(mp, inp["t0"] + k * inp["dt"], inp["dt"], inp["nH"], inp["src"],
+                              E, e, y, tol=tol)
+        return E, e, y
+    return cached(("mg_traj", name, tol), run)
+
+
+def _gpu_traj(name, w, mp, inp, dev, **prm):
+    s = _solver(w, mp, dev, **prm)
+    nH, src = to_dev(inp["nH"], dev), to_dev(inp["src"], dev)
+    E, e, y = _gpu_state(inp, dev, mp.base.isothermal)
+    stats = []
+    for k in range(inp["nsteps"]):
+        stats.append(s.step(inp["t0"] + k * inp["dt"], inp["dt"], nH, src, E, e, y))
+    s.close()
+    return (E.cpu().numpy(), None if e is None else e.cpu().numpy(), y.cpu().numpy()), stats
+
+
+def _traj_errors(g, o, mp, nH):
+    Eg, eg, yg = g
+    Eo, eo, yo = o
+    err = {f"E{k}": elementwise(Eg[k], Eo[k], 1e-12) for k in range(mp.G)}
+    # species relative to their element's density (x floor 1e-6 as the grey tests)
+    err["x_HI"] = float(np.max(np.abs(yg[0] - yo[0]) / nH / np.maximum(1 - yo[0] / nH, 1e-6)))
+    if mp.he:
+        nHe = mp.y_he * nH
+        err["HeI"] = float(np.max(np.abs(yg[1] - yo[1]) / nHe))
+        err["HeII"] = float(np.max(np.abs(yg[2] - yo[2]) / nHe))
+    if eg is not None:
+        err["e"] = float(np.max(np.abs(eg - eo) / np.abs(eo)))
+    return err
+
+
+TRAJ_CASES = [n for n, c in MG_CASES.items() if c[5] > 0]
+
+
+@pytest.mark.parametrize("name", TRAJ_CASES)
+def test_step_parity_fp64(hip_device, name):
+    w, mp, inp = _setup(name, newton_tol=1e-12)
+    o = _oracle_traj(name, mp, inp, 1e-12)
+    g, st = _gpu_traj(name, w, mp, inp, hip_device, newton_tol=1e-12, precision=0)
+    err = _traj_errors(g, o, mp, inp["nH"])
+    print(name, "fp64", {k: f"{v:.1e}" for k, v in err.items()},
+          [(s["newton_its"], s["lin_its_total"], s["lin_its_max"]) for s in st])
+    assert max(err.values()) < 1e-10
+    assert all(s["lin_cap_hits"] == 0 for s in st)
+
+
+@pytest.mark.parametrize("name", ["he3_lognormal", "he4_eds", "he3_lcdm"])
+def test_step_parity_mixed(hip_device, name):
+    w, mp, inp = _setup(name, newton_tol=1e-12)
+    o = _oracle_traj(name, mp, inp, 1e-12)
+    g, st = _gpu_traj(name, w, mp, inp, hip_device, newton_tol=1e-12, precision=1)
+    err = _traj_errors(g, o, mp, inp["nH"])
+    print(name, "mixed", {k: f"{v:.1e}" for k, v in err.items()},
+          [(s["newton_its"], s["lin_its_total"], s["lin_its_max"]) for s in st])
+    assert max(err.values()) < 1e-6
+
+
+@pytest.mark.parametrize("cfg,dims", [(2, (24, 20, 36)), (1, (16, 16, 16))])
+def test_one_group_without_helium_is_the_grey_gpu_step(hip_device, cfg, dims):
+    """G = 1, y_He = 0: the multigroup step solves the grey step's equations
+    (the local block reduces to (e, n_HI) and the group constants to the
+    grey ones), so both GPU paths reach the same root."""
+    import paper_0908_2654_amd as P
+    w = W.scaled(cfg, dims)
+    p = P.params_from_workload(w, newton_tol=1e-12, precision=0)
+    op = OM.params_from_workload(w)
+    nH = W.density_field(w)
+    src = OM.source_field(op, W.photon_rate_field(w))
+    t0, dt, _ = OM.schedule(op, w)
+    E, e, n = OM.initial_state(op, nH, w.x0, w.T0, w.E0)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    grey = P.Solver(p, device=hip_device)
+    mgs = P.MultigroupSolver(p, P.multigroup_params((p.hnu0_eV,), 0.0), device=hip_device)
+    nHd, srcd = d(nH), d(src)
+    Eg, eg, ng = d(E), d(e), d(n)
+    Em, em = d(E[None]), d(e)
+    ym = d(np.stack([n, 0 * n, 0 * n]))
+    for k in range(3):
+        grey.step(t0 + k * dt, dt, nHd, srcd, Eg, eg, ng)
+        mgs.step(t0 + k * dt, dt, nHd, srcd, Em, em, ym)
+        a = (Eg.cpu().numpy(), eg.cpu().numpy(), ng.cpu().numpy())
+        b = (Em.cpu().numpy()[0], em.cpu().numpy(), ym.cpu().numpy()[0])
+        eE = elementwise(b[0], a[0], 1e-12)
+        ee = float(np.max(np.abs(b[1] - a[1]) / a[1]))
+        ex = float(np.max(np.abs(b[2] - a[2]) / nH / np.maximum(1 - a[2] / nH, 1e-6)))
+        print(k, eE, ee, ex)
+        assert max(eE, ee, ex) < 1e-10
+        assert np.all(ym.cpu().numpy()[1:] == 0.0)
+    grey.close()
+    mgs.close()
+
+
+def test_step_restores_state_on_failure_and_rejects_bad_arguments(hip_device):
+    from paper_0908_2654_amd import _lib
+    w, mp, inp = _setup("he3_lognormal")
+    s = _solver(w, mp, hip_device, newton_max_it=1, newton_tol=1e-14)
+    nH, src = to_dev(inp["nH"], hip_device), to_dev(inp["src"], hip_device)
+    E, e, y = _gpu_state(inp, hip_device, False)
+    E0, e0, y0 = E.clone(), e.clone(), y.clone()
+    with pytest.raises(_lib.RhError) as ex:
+        s.step(inp["t0"], inp["dt"], nH, src, E, e, y)
+    assert ex.value.status == _lib.RH_ENEWTON
+    assert E.equal(E0) and e.equal(e0) and y.equal(y0)
+    with pytest.raises(_lib.RhError) as ex:
+        s.step(inp["t0"], -1.0, nH, src, E, e, y)
+    assert ex.value.status == _lib.RH_EINVAL
+    s.close()
