@@ -277,6 +277,117 @@ def cpu_baseline(w, nH_full, state, t, dt, sub=64):
     }
 
 
+MG_EDGES_EV = (13.6, 24.587, 54.4)   # groups split at the HeI and HeII thresholds
+MG_Y_HE = 0.08                        # n_He / n_H (primordial helium by number)
+
+
+def cpu_baseline_multigroup(w, nH_full, Q_full, state, t, dt, sub=8):
+    """The multigroup oracle on a bounded sample: one step of a sub^3 block
+    cut from the GPU state at the start of the first timed step (closed
+    periodically, R_min of the whole box), one BLAS thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import model as OM, multigroup as OMG
+    ws = W.get(w)
+    ws.dims = (sub, sub, sub)
+    ws.box_comoving_cm = w.box_comoving_cm * sub / w.dims[0]
+    ws.bc = (W.BC_PERIODIC,) * 6
+    cut = (slice(0, sub),) * 3
+    a_n = OM.params_from_workload(w).cosmo.a(t)
+    mp = OMG.params_from_workload(ws, MG_EDGES_EV, MG_Y_HE, newton_tol=1e-8,
+                                  R_min=1.0 / (a_n * w.box_comoving_cm))
+    nH = np.ascontiguousarray(nH_full[cut])
+    src = OM.source_field(mp.base, np.ascontiguousarray(Q_full[cut]))
+    E, e, y = state
+    E = np.ascontiguousarray(E.cpu().numpy()[(slice(None),) + cut])
+    e = np.ascontiguousarray(e.cpu().numpy()[cut])
+    y = np.ascontiguousarray(y.cpu().numpy()[(slice(None),) + cut])
+    st = {}
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        OMG.step(mp, t, dt, nH, src, E, e, y, stats=st)
+        el = time.perf_counter() - t1
+    return {"value": sub ** 3 / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one multigroup step (Newton to ||f|| <= 1e-8, {st['newton_its']} "
+                      f"iterations, sparse direct solves) of a {sub}^3 block of the GPU state at "
+                      f"the start of the first timed step, {el:.1f} s on one thread",
+            "host": host_description()}
+
+
+def run_multigroup(args, dev):
+    """Time the hydrogen + helium multigroup step (rh_multigroup_step) on the
+    configured workload: three groups split at the helium thresholds,
+    n_He / n_H = 0.08, mixed precision, Newton to 1e-8 with forcing 1e-13."""
+    import numpy as np
+    import torch
+
+    import paper_0908_2654_amd as P
+    import workloads as W
+    from paper_0908_2654_amd.inputs import schedule
+    w = W.get(args.config)
+    prm = P.params_from_workload(w, precision=1, **MG)
+    mgp = P.multigroup_params(MG_EDGES_EV, MG_Y_HE)
+    log(f"multigroup workload {w.name} dims={w.dims}: generating inputs")
+    nH_host = W.density_field(w)
+    Q_host = W.photon_rate_field(w)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)  # noqa: E731
+    nH = to(nH_host)
+    src = torch.empty_like(nH)
+    g = P.Solver(prm, device=dev)          # the source field uses the grey mean photon energy
+    g.source_field(to(Q_host), src)
+    g.close()
+    del g
+    s = P.MultigroupSolver(prm, mgp, device=dev)
+    E, e, y = s.empty_state()
+    s.initial_state(nH, w.x0, w.T0, w.E0, E, e, y)
+    t0, dt, nsteps = schedule(w, prm)
+    for k in range(args.warmup):
+        st = s.step(t0 + k * dt, dt, nH, src, E, e, y)
+        log(f"  warmup step {k}: newton={st['newton_its']} its={st['lin_its_total']} "
+            f"sweeps<={st['lin_its_max']}")
+    t_start = t0 + args.warmup * dt
+    state0 = (E.clone(), e.clone(), y.clone())
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(s.step(t_start + k * dt, dt, nH, src, E, e, y))
+        x = stats[-1]
+        log(f"  step {k}: newton={x['newton_its']} multigrid its={x['lin_its_total']} "
+            f"sweeps<={x['lin_its_max']} caps={x['lin_cap_hits']} res={x['res_final']:.2e} "
+            f"gpu_ms={x['t_ms'][0]:.1f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    s.close()
+    N = w.ncells
+    value = N * args.steps / wall / 1e6
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (multigroup oracle on a bounded sample)")
+        cpu = cpu_baseline_multigroup(w, nH_host, Q_host, state0, t_start, dt)
+        log(f"cpu baseline: {cpu['value']:.5f} Mcell-updates/s")
+    return {
+        "metric": "Mcell-updates/s per multigroup implicit step (3 groups, H + He) at 1e-8 residual",
+        "value": round(value, 2), "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 multigrid / f64 refinement", "data": "synthetic",
+        "config": {"workload": w.name + "_3groups_he", "grid": list(w.dims),
+                   "sources": w.n_sources, "group_edges_eV": list(MG_EDGES_EV), "y_he": MG_Y_HE,
+                   "newton_tol": 1e-8, "lin_forcing": 1e-13,
+                   "linear": "block Gauss-Seidel over groups, PCG + V(2,2) per group"},
+        "per_step": {"newton_its": [x["newton_its"] for x in stats],
+                     "multigrid_its": [x["lin_its_total"] for x in stats],
+                     "sweeps_max": [x["lin_its_max"] for x in stats],
+                     "lin_res_max": [float(f"{x['lin_res_max']:.3g}") for x in stats],
+                     "lin_cap_hits": [x["lin_cap_hits"] for x in stats],
+                     "gpu_ms": [round(x["t_ms"][0], 1) for x in stats]},
+        "cpu_baseline": cpu,
+    }
+
+
 def copy_bandwidth(dev, reps=5):
     """GB/s of a plain 1 GiB device-to-device copy (bytes read + written per
     second): the practical HBM ceiling of the box, for context."""
@@ -315,6 +426,8 @@ def main():
                     help="box radius of the block smoother around sources (0 off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--multigroup", action="store_true",
+                    help="time the hydrogen + helium multigroup step instead (its own line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the step has no multi-GPU path",
@@ -340,9 +453,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 << 28, "launches": 3}))
         return
-    w = W.get(args.config)
     MG.update(mg_pre=args.mg_pre, mg_post=args.mg_post, smoother=args.smoother,
               mg_block_radius=args.block_radius)
+    if args.multigroup:
+        print(json.dumps(run_multigroup(args, dev)), flush=True)
+        return
+    w = W.get(args.config)
     log(f"workload {w.name} dims={w.dims}: generating inputs")
     tg = time.perf_counter()
     nH_host = W.density_field(w)

@@ -446,11 +446,13 @@ void rh_destroy(rh_handle* h);
  *    fewer without helium), weights E_s of each group (as the grey E_s),
  *    e^n, n_H for n_HI and n_He for the helium species.
  * Solver: Newton with the local unknowns eliminated per cell.  The Schur
- * system couples the groups only within a cell; it is solved by block
- * Gauss-Seidel over the groups (at most lin_max_it sweeps), each group's
- * 7-point system by the configured multigrid solve to 1/50 of its current
- * residual, until the coupled residual is below lin_forcing ||f||.
- * Isothermal runs accept e == NULL. */
+ * system couples the groups only within a cell; it is solved by flexible
+ * GMRES (restart 8, the norm's weights in its inner product), preconditioned
+ * by one block Gauss-Seidel sweep over the groups in which each group's
+ * 7-point system is solved by the configured multigrid to 1/50 of its
+ * residual, until the coupled residual is below lin_forcing ||f|| or at its
+ * FP64 rounding floor (1e-15 of the RMS of the terms it sums), for at most
+ * lin_max_it sweeps.  Isothermal runs accept e == NULL. */
 #define RH_MAX_GROUPS 4
 typedef struct rh_multigroup_params {
   int32_t groups;                /* 1 .. RH_MAX_GROUPS                                  */
@@ -490,9 +492,11 @@ rh_status rh_multigroup_initial_state(rh_multigroup* h, const double* nH, double
  * E, e, y hold U^n; out: U^{n+1}.  On RH_ENEWTON, RH_ELINEAR or
  * RH_ENONFINITE they are restored to U^n.  stats (may be NULL) as for
  * rh_implicit_step, except lin_its_total (multigrid iterations over all
- * groups and sweeps), lin_its_max (most block Gauss-Seidel sweeps of one
- * Newton iteration) and lin_cap_hits (Newton iterations whose coupled solve
- * stopped above its target); t_ms[1..5] are 0. */
+ * groups and sweeps), lin_its_max (most preconditioner sweeps of one Newton
+ * iteration), lin_cap_hits (Newton iterations whose coupled solve stopped
+ * above both its target and its rounding floor) and lin_res_max (largest
+ * ratio of the final coupled residual to ||f||, floor stops included);
+ * t_ms[1..5] are 0. */
 rh_status rh_multigroup_step(rh_multigroup* h, double t_n_s, double dt_s, const double* nH,
                              const double* src, double* E, double* e, double* y,
                              rh_step_stats* stats);

@@ -447,6 +447,158 @@ k_group_coupled(StepK k, int G, int g, const double* __restrict__ rS,
 }
 
 __global__ void __launch_bounds__(kBlock)
+k_groups_coupled(StepK k, int G, GroupOps o, const double* __restrict__ K,
+                 const double* __restrict__ x, double* __restrict__ B,
+                 double* __restrict__ part) {
+  const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
+                      k.bc[4] == RH_BC_PERIODIC};
+  const int nd[3] = {k.nx, k.ny, k.nz};
+  const long long N = k.N;
+  double sw = 0.0, sm = 0.0;
+  for (long long idx = xcd_tile(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x;
+       idx < N; idx += (long long)blockDim.x * gridDim.x) {
+    int c[3];
+    cell_ijk(idx, k.ny, k.nz, c[0], c[1], c[2]);
+    long long Qp[3], Qm[3];
+    bool hp[3], hm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int q[3];
+      hp[d] = neighbour(c, nd, per, d, +1, q);
+      Qp[d] = hp[d] ? cell_index(q[0], q[1], q[2], k.ny, k.nz) : idx;
+      hm[d] = neighbour(c, nd, per, d, -1, q);
+      Qm[d] = hm[d] ? cell_index(q[0], q[1], q[2], k.ny, k.nz) : idx;
+    }
+    double xv[kMaxGroups];
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; ++g) xv[g] = g < G ? x[g * N + idx] : 0.0;
+#pragma unroll
+    for (int g = 0; g < kMaxGroups; ++g) {
+      if (g >= G) continue;
+      const double* xg = x + g * N;
+      double t = o.diag[g][idx] * xv[g];
+      double Sx = t, mag = fabs(t);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (hp[d]) {
+          t = o.cf[g][d][idx] * xg[Qp[d]];
+          Sx -= t;
+          mag += fabs(t);
+        }
+        if (hm[d]) {
+          t = o.cf[g][d][Qm[d]] * xg[Qm[d]];
+          Sx -= t;
+          mag += fabs(t);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < kMaxGroups; ++h)
+        if (h < G && h != g) {
+          t = K[((long long)g * G + h) * N + idx] * xv[h];
+          Sx -= t;
+          mag += fabs(t);
+        }
+      double r = Sx;
+      if (o.rS[g]) {
+        r = o.rS[g][idx] - Sx;
+        mag += fabs(o.rS[g][idx]);
+      }
+      B[g * N + idx] = r;
+      const double iw = 1.0 / o.E_s[g];
+      sw += (r * iw) * (r * iw);
+      sm += (mag * iw) * (mag * iw);
+    }
+  }
+  double v[2] = {sw, sm};
+  const int im[2] = {0, 0};
+  const int sl[2] = {RS_FE2, RS_MAG2};
+  block_reduce_store<2>(v, im, sl, part);
+}
+
+// Weighted inner products <u, v>_W = sum_g sum_P u v / E_s,g^2 over [G][N]
+// vectors: one partial sum per workgroup and vector, out[i * grid + block].
+__global__ void __launch_bounds__(kBlock)
+k_wdots(long long N, int G, WeightK wk, const double* __restrict__ u,
+        const double* __restrict__ V, long long stride, int nv, double* __restrict__ out) {
+  double acc[kKrylovMax];
+#pragma unroll
+  for (int i = 0; i < kKrylovMax; ++i) acc[i] = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double wg = wk.w[g];
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)blockDim.x * gridDim.x) {
+      const double ug = u[g * N + idx] * wg;
+#pragma unroll
+      for (int i = 0; i < kKrylovMax; ++i)
+        if (i < nv) acc[i] += ug * V[i * stride + g * N + idx];
+    }
+  }
+  __shared__ double sh[kKrylovMax][kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kKrylovMax; ++i) {
+    if (i >= nv) continue;
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) sh[i][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[threadIdx.x][w];
+    out[threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// y = a y + sum_{i < nv} c_i V_i over [G][N] vectors; with norm_part != NULL
+// also the workgroup partials of ||y||_W^2 (after the update).
+__global__ void __launch_bounds__(kBlock)
+k_wcombine(long long N, int G, WeightK wk, double* __restrict__ y, double a,
+           const double* __restrict__ V, long long stride, int nv, Coefs cs,
+           double* __restrict__ norm_part) {
+  double sn = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double wg = wk.w[g];
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < N;
+         idx += (long long)blockDim.x * gridDim.x) {
+      const long long o = g * N + idx;
+      double v = a == 0.0 ? 0.0 : a * y[o];
+#pragma unroll
+      for (int i = 0; i < kKrylovMax; ++i)
+        if (i < nv) v += cs.c[i] * V[i * stride + o];
+      y[o] = v;
+      sn += v * v * wg;
+    }
+  }
+  if (!norm_part) return;
+  __shared__ double sh[kBlock / 64];
+  const double v = wave_sum(sn);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+    norm_part[blockIdx.x] = t;
+  }
+}
+
+// out[i] = sum over the grid's partials of vector i, in a fixed order (one
+// workgroup per vector; out may be mapped host memory).
+__global__ void __launch_bounds__(kBlock)
+k_wsum(const double* __restrict__ part, int grid, double* __restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < grid; b += kBlock) v += part[blockIdx.x * grid + b];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+    out[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
 k_groups_init(long long N, GroupK m, double f0, double f1, double f2, double f3, double E0,
               double x0, double e0, const double* __restrict__ nH, double* __restrict__ E,
               double* __restrict__ e, double* __restrict__ y, double* __restrict__ part) {
@@ -485,6 +637,27 @@ void launch_group_coupled(hipStream_t s, const StepK& k, int G, int g, const dou
                           const double* x, double* b, double* part) {
   hipLaunchKernelGGL(k_group_coupled, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, G, g, rS, diag,
                      cf[0], cf[1], cf[2], K, x, b, part);
+}
+
+void launch_groups_coupled(hipStream_t s, const StepK& k, int G, const GroupOps& o,
+                           const double* K, const double* x, double* B, double* part) {
+  hipLaunchKernelGGL(k_groups_coupled, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, G, o, K, x, B,
+                     part);
+}
+
+void launch_wdots(hipStream_t s, long long N, int G, const WeightK& wk, const double* u,
+                  const double* V, long long stride, int nv, double* part, double* out) {
+  hipLaunchKernelGGL(k_wdots, dim3(kKrylovGrid), dim3(kBlock), 0, s, N, G, wk, u, V, stride, nv,
+                     part);
+  hipLaunchKernelGGL(k_wsum, dim3(nv), dim3(kBlock), 0, s, part, kKrylovGrid, out);
+}
+
+void launch_wcombine(hipStream_t s, long long N, int G, const WeightK& wk, double* y, double a,
+                     const double* V, long long stride, int nv, const Coefs& c, double* part,
+                     double* norm_out) {
+  hipLaunchKernelGGL(k_wcombine, dim3(kKrylovGrid), dim3(kBlock), 0, s, N, G, wk, y, a, V, stride,
+                     nv, c, norm_out ? part : nullptr);
+  if (norm_out) hipLaunchKernelGGL(k_wsum, dim3(1), dim3(kBlock), 0, s, part, kKrylovGrid, norm_out);
 }
 
 void launch_groups_init(hipStream_t s, long long N, const GroupK& m, const double* frac, double E0,

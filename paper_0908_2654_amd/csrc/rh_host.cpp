@@ -1874,6 +1874,8 @@ namespace {
 constexpr double kHeIThresholdEV = 24.587;  // HeI ionisation threshold
 constexpr double kHeISigma0 = 7.42e-18;     // HeI threshold cross-section, cm^2
 constexpr double kInnerReduction = 0.02;    // a group's solve: residual / 50 per sweep
+constexpr int kRestart = 8;                 // flexible GMRES restart length
+static_assert(kRestart + 1 <= kKrylovMax, "Krylov kernels combine at most kKrylovMax vectors");
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on the
 // Legendre polynomial P_n from cosine first guesses.
@@ -1999,7 +2001,7 @@ GroupConsts group_constants(const rh_params& p, const rh_multigroup_params& mg) 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // coupled fields of the multigroup handle, in units of one N-cell FP64 field
-int group_fields(int G) { return G * G + 12 * G + 17; }
+int group_fields(int G) { return G * G + (12 + 2 * kRestart + 1) * G + 17; }
 
 struct GState {
   double* E;   // [G][N]
@@ -2034,6 +2036,9 @@ struct rh_multigroup {
   double *K = nullptr, *kB = nullptr;                   // Schur coupling [G][G][N], [G][N]
   double *dE = nullptr;                                 // Newton direction [G][N]
   double *b = nullptr;                                  // right-hand side of a group solve
+  double *KV = nullptr, *KZ = nullptr;                  // Krylov bases [kRestart + 1][G][N], [kRestart][G][N]
+  double *kpart = nullptr;                              // Krylov reduction partials
+  double *kred = nullptr, *kred_dev = nullptr;          // their sums (mapped host memory)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::string err;
   int local_its_max = 0;
@@ -2169,12 +2174,14 @@ rh_status groups_eval(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const GSt
   return RH_OK;
 }
 
-// Coupled Schur residual of group g at h->dE into h->b; returns the
-// weighted sum of squares and max |b| through fe2 / rmax.
-rh_status coupled_residual(rh_multigroup* h, const StepK& k, int g, double& fe2, double& rmax) {
+// Coupled residual of group g for the right-hand side rhs at x into h->b:
+// b = rhs_g - S_gg x_g + sum_{h != g} K_gh x_h, with its weighted sum of
+// squares and max |b|.
+rh_status coupled_residual(rh_multigroup* h, const StepK& k, int g, const double* rhs,
+                           const double* x, double& fe2, double& rmax) {
   rh_handle* s = h->sub[g];
   const double* cf[3] = {s->cf64[0], s->cf64[1], s->cf64[2]};
-  launch_group_coupled(h->stream, k, h->G, g, s->rS, s->diag64, cf, h->K, h->dE, h->b, s->part);
+  launch_group_coupled(h->stream, k, h->G, g, rhs, s->diag64, cf, h->K, x, h->b, s->part);
   GHIPCHK(hipGetLastError());
   rh_status st = sync_reductions(s, slot_bit(RS_FE2) | slot_bit(RS_R2) | slot_bit(RS_RMAX));
   if (st != RH_OK) return sub_fail(h, g, st);
@@ -2183,74 +2190,154 @@ rh_status coupled_residual(rh_multigroup* h, const StepK& k, int g, double& fe2,
   return RH_OK;
 }
 
-// Block Gauss-Seidel over the groups on the coupled Schur system
-//   S_gg dE_g - sum_{h != g} K_gh dE_h = rS_g,
-// each group's correction from its own multigrid solve.  Stops when the
-// weighted norm of the coupled residual is <= target, after max_sweeps, or
-// on stagnation.
+// Preconditioner of the coupled solve: z = one block Gauss-Seidel sweep over
+// the groups from z = 0 for the right-hand side v ([G][N]); group g's
+// correction solves S_gg c = v_g - S_gg z_g + sum_{h != g} K_gh z_h with its
+// own multigrid to kInnerReduction of that residual.
+rh_status groups_precondition(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const double* v,
+                              double* z, int& its_total) {
+  const long long N = h->N;
+  GHIPCHK(hipMemsetAsync(z, 0, sizeof(double) * h->G * N, h->stream));
+  for (int g = 0; g < h->G; ++g) {
+    double fe2 = 0.0, rmax = 0.0;
+    rh_status st = coupled_residual(h, kg[g], g, v + g * N, z, fe2, rmax);
+    if (st != RH_OK) return st;
+    if (rmax == 0.0) continue;
+    rh_handle* s = h->sub[g];
+    const double wsub = std::sqrt(fe2 / (N * nvars(s)));
+    double* keep = s->rS;
+    s->rS = h->b;
+    double* x = nullptr;
+    int its = 0;
+    double wi = 0.0, l2 = 0.0;
+    bool reached = true;
+    st = solve_linear(s, kg[g], rmax, kInnerReduction * wsub, 0.0, s->p.lin_max_it, &x, &its, &wi,
+                      &l2, &reached);
+    s->rS = keep;
+    s->keep_coarse = true;
+    if (st != RH_OK) return sub_fail(h, g, st);
+    its_total += its;
+    launch_xaxpy(h->stream, N, 1.0, x, z + g * N, 0);
+    GHIPCHK(hipGetLastError());
+  }
+  return RH_OK;
+}
+
+// Flexible GMRES(kRestart) on the coupled Schur system
+//   S_gg dE_g - sum_{h != g} K_gh dE_h = rS_g   (g = 1..G)
+// in the inner product of the norm's weights, right-preconditioned by one
+// block Gauss-Seidel sweep (groups_precondition).  Stops when the weighted
+// RMS of the true residual is <= target or at its FP64 rounding floor
+// (1e-15 of the RMS of the magnitudes of the terms it sums), or after
+// max_sweeps preconditioner applications.
 rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double target,
                        int max_sweeps, int& its_total, int& sweeps, bool& reached,
                        double& w_final) {
   const long long N = h->N;
+  const int G = h->G;
+  const long long GN = (long long)G * N;
   const double scale = 1.0 / (N * group_nvars(h));
-  GHIPCHK(hipMemsetAsync(h->dE, 0, sizeof(double) * h->G * N, h->stream));
-  for (int g = 0; g < h->G; ++g) h->sub[g]->keep_coarse = false;
-  double prev = INFINITY;
-  int slow = 0;
-  reached = false;
+  rh_handle* s0 = h->sub[0];
+  GroupOps ops{};
+  WeightK wk{};
+  for (int g = 0; g < G; ++g) {
+    ops.rS[g] = h->sub[g]->rS;
+    ops.diag[g] = h->sub[g]->diag64;
+    for (int d = 0; d < 3; ++d) ops.cf[g][d] = h->sub[g]->cf64[d];
+    ops.E_s[g] = kg[g].E_s;
+    wk.w[g] = 1.0 / (kg[g].E_s * kg[g].E_s);
+  }
+  GroupOps apply = ops;  // the operator alone: B = S x
+  for (int g = 0; g < G; ++g) apply.rS[g] = nullptr;
+  GHIPCHK(hipMemsetAsync(h->dE, 0, sizeof(double) * GN, h->stream));
+  for (int g = 0; g < G; ++g) h->sub[g]->keep_coarse = false;
   its_total = 0;
+  sweeps = 0;
+  reached = false;
+  const Coefs none{};
+  double* V = h->KV;   // basis, kRestart + 1 vectors of G N
+  double* Z = h->KZ;   // preconditioned basis, kRestart vectors
+  double* hv = h->kred;  // mapped host memory the Krylov reductions write
   rh_status st = RH_OK;
-  int sweep = 0;
-  for (;; ++sweep) {
-    // every group's residual at dE (group 0 last: its b starts the sweep)
-    double fe2[kMaxGroups], rmax[kMaxGroups], tot = 0.0;
-    for (int g = h->G - 1; g >= 0; --g) {
-      if ((st = coupled_residual(h, kg[g], g, fe2[g], rmax[g])) != RH_OK) break;
-      tot += fe2[g];
-    }
-    if (st != RH_OK) break;
-    const double w = std::sqrt(tot * scale);
+  for (int restart = 0;; ++restart) {
+    // true residual V_0 = rS - S dE and its norm
+    launch_groups_coupled(h->stream, kg[0], G, ops, h->K, h->dE, V, s0->part);
+    GHIPCHK(hipGetLastError());
+    if ((st = sync_reductions(s0, slot_bit(RS_FE2) | slot_bit(RS_MAG2))) != RH_OK)
+      return sub_fail(h, 0, st);
+    const double rr = s0->hred[RS_FE2];
+    const double floor = 1e-15 * std::sqrt(s0->hred[RS_MAG2] * scale);
+    const double w = std::sqrt(rr * scale);
     w_final = w;
-    if (!std::isfinite(w)) {
-      st = gfail(h, RH_ELINEAR, "non-finite coupled linear residual");
-      break;
-    }
-    if (w <= target) {
+    if (!std::isfinite(w)) return gfail(h, RH_ELINEAR, "non-finite coupled linear residual");
+    if (w <= target || w <= floor) {
       reached = true;
       break;
     }
-    if (sweep >= max_sweeps) break;
-    slow = w > 0.9 * prev ? slow + 1 : 0;
-    if (slow >= 3) break;  // stagnated at the rounding floor
-    prev = w;
-    for (int g = 0; g < h->G && st == RH_OK; ++g) {
-      if (g > 0 && (st = coupled_residual(h, kg[g], g, fe2[g], rmax[g])) != RH_OK) break;
-      if (rmax[g] == 0.0) continue;
-      rh_handle* s = h->sub[g];
-      const double wsub = std::sqrt(fe2[g] / (N * nvars(s)));
-      double* keep = s->rS;
-      s->rS = h->b;
-      double* x = nullptr;
-      int its = 0;
-      double wi = 0.0, l2 = 0.0;
-      bool r_in = true;
-      st = solve_linear(s, kg[g], rmax[g], kInnerReduction * wsub, 0.0, s->p.lin_max_it, &x, &its,
-                        &wi, &l2, &r_in);
-      s->rS = keep;
-      s->keep_coarse = true;
-      if (st != RH_OK) {
-        st = sub_fail(h, g, st);
-        break;
+    if (sweeps >= max_sweeps) break;
+    const double beta = std::sqrt(rr);
+    launch_wcombine(h->stream, N, G, wk, V, 1.0 / beta, nullptr, 0, 0, none, h->kpart, nullptr);
+    GHIPCHK(hipGetLastError());
+    double H[kRestart + 1][kRestart] = {};
+    double cs[kRestart] = {}, sn[kRestart] = {}, gv[kRestart + 1] = {};
+    gv[0] = beta;
+    int kdim = 0;
+    for (int j = 0; j < kRestart; ++j) {
+      if ((st = groups_precondition(h, kg, V + j * GN, Z + j * GN, its_total)) != RH_OK) return st;
+      ++sweeps;
+      double* Vn = V + (j + 1) * GN;
+      launch_groups_coupled(h->stream, kg[0], G, apply, h->K, Z + j * GN, Vn, s0->part);
+      GHIPCHK(hipGetLastError());
+      // classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_wdots(h->stream, N, G, wk, Vn, V, GN, j + 1, h->kpart, h->kred_dev);
+        GHIPCHK(hipGetLastError());
+        GHIPCHK(hipStreamSynchronize(h->stream));
+        Coefs c{};
+        for (int i = 0; i <= j; ++i) {
+          c.c[i] = -hv[i];
+          H[i][j] += hv[i];
+        }
+        launch_wcombine(h->stream, N, G, wk, Vn, 1.0, V, GN, j + 1, c, h->kpart,
+                        pass == 1 ? h->kred_dev : nullptr);
+        GHIPCHK(hipGetLastError());
       }
-      its_total += its;
-      launch_xaxpy(h->stream, N, 1.0, x, h->dE + g * N, 0);
-      if (hipGetLastError() != hipSuccess) st = gfail(h, RH_EHIP, "launch failed (direction update)");
+      GHIPCHK(hipStreamSynchronize(h->stream));
+      const double hn = std::sqrt(std::max(hv[0], 0.0));
+      H[j + 1][j] = hn;
+      if (hn > 0.0) {
+        launch_wcombine(h->stream, N, G, wk, Vn, 1.0 / hn, nullptr, 0, 0, none, h->kpart, nullptr);
+        GHIPCHK(hipGetLastError());
+      }
+      // Givens rotations: H upper triangular, gv the rotated right-hand side
+      for (int i = 0; i < j; ++i) {
+        const double a = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
+        H[i + 1][j] = -sn[i] * H[i][j] + cs[i] * H[i + 1][j];
+        H[i][j] = a;
+      }
+      const double den = std::hypot(H[j][j], H[j + 1][j]);
+      cs[j] = den > 0.0 ? H[j][j] / den : 1.0;
+      sn[j] = den > 0.0 ? H[j + 1][j] / den : 0.0;
+      H[j][j] = den;
+      H[j + 1][j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      kdim = j + 1;
+      const double est = std::fabs(gv[j + 1]) * std::sqrt(scale);
+      if (est <= target || est <= floor || hn == 0.0 || sweeps >= max_sweeps) break;
     }
-    if (st != RH_OK) break;
+    // dE += sum_i y_i Z_i with H y = gv (upper triangular, kdim x kdim)
+    Coefs y{};
+    for (int i = kdim - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int l = i + 1; l < kdim; ++l) t -= H[i][l] * y.c[l];
+      y.c[i] = H[i][i] != 0.0 ? t / H[i][i] : 0.0;
+    }
+    launch_wcombine(h->stream, N, G, wk, h->dE, 1.0, Z, GN, kdim, y, h->kpart, nullptr);
+    GHIPCHK(hipGetLastError());
   }
-  for (int g = 0; g < h->G; ++g) h->sub[g]->keep_coarse = false;
-  sweeps = sweep;
-  return st;
+  for (int g = 0; g < G; ++g) h->sub[g]->keep_coarse = false;
+  return RH_OK;
 }
 
 rh_status groups_copy(rh_multigroup* h, double* E, double* e, double* y, const double* Es,
@@ -2310,9 +2397,10 @@ size_t rh_multigroup_workspace_bytes(const rh_params* p, const rh_multigroup_par
     return 0;
   }
   const size_t N = (size_t)p->nx * p->ny * p->nz;
-  // 14 arrays of whole fields, each rounded up to 256 bytes
+  // 16 arrays of whole fields and the Krylov partials, each rounded up to 256 bytes
   return 256 + mg->groups * round256(rh_workspace_bytes(p)) +
-         group_fields(mg->groups) * sizeof(double) * N + 14 * 256;
+         group_fields(mg->groups) * sizeof(double) * N + 16 * 256 +
+         round256(sizeof(double) * kKrylovMax * kKrylovGrid);
 }
 
 rh_status rh_multigroup_setup(const rh_params* p, const rh_multigroup_params* mg, void* workspace,
@@ -2385,6 +2473,16 @@ rh_status rh_multigroup_setup(const rh_params* p, const rh_multigroup_params* mg
   h->kB = take_block(G);
   h->dE = take_block(G);
   h->b = take_block(1);
+  h->KV = take_block((kRestart + 1) * G);
+  h->KZ = take_block(kRestart * G);
+  h->kpart = reinterpret_cast<double*>(base);
+  base += round256(sizeof(double) * kKrylovMax * kKrylovGrid);
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->kred), sizeof(double) * kKrylovMax) != hipSuccess ||
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&h->kred_dev), h->kred, 0) != hipSuccess) {
+    rh_multigroup_destroy(h);
+    set_global_error("hipHostMalloc failed");
+    return RH_EHIP;
+  }
   if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
     rh_multigroup_destroy(h);
     set_global_error("hipEventCreate failed");
@@ -2533,6 +2631,7 @@ const char* rh_multigroup_last_error(const rh_multigroup* h) {
 void rh_multigroup_destroy(rh_multigroup* h) {
   if (!h) return;
   for (int g = 0; g < kMaxGroups; ++g) rh_destroy(h->sub[g]);
+  if (h->kred) (void)hipHostFree(h->kred);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;

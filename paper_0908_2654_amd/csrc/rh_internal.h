@@ -100,6 +100,7 @@ enum RedSlot {
   RS_CHG2,         // sum of squared weighted changes U^{n+1} - U^n (step controller)
   RS_NEGE,         // max over cells of -E/E_s (positivity check)
   RS_COURANT,      // max over cells of the outgoing Courant number (advection)
+  RS_MAG2,         // sum of squared weighted term magnitudes (coupled multigroup residual)
   RS_COUNT
 };
 static_assert(RS_COUNT <= 32, "slot masks are 32-bit");
@@ -273,6 +274,7 @@ void launch_block_relax(hipStream_t s, const LevelK<T>& l, const BlockSet<T>& bs
 // group after group ([G][N]); species fields [3][N] (n_HI, n_HeI, n_HeII).
 constexpr int kMaxGroups = RH_MAX_GROUPS;
 constexpr int kLoc = 4;
+static_assert(kMaxGroups <= kLoc, "the local solves share one 4 x 4 elimination");
 struct GroupK {
   int G;                              // groups
   int he;                             // helium present (y_he > 0)
@@ -305,6 +307,40 @@ void launch_local_groups(hipStream_t s, const StepK& k, const GroupK& m, const G
 void launch_group_coupled(hipStream_t s, const StepK& k, int G, int g, const double* rS,
                        const double* diag, const double* const cf[3], const double* K,
                        const double* x, double* b, double* part);
+// The G groups' Schur operators (diagonal and + face coefficients, each on
+// its own grey handle), right-hand sides and norm scales.
+struct GroupOps {
+  const double* rS[kMaxGroups];
+  const double* diag[kMaxGroups];
+  const double* cf[kMaxGroups][3];
+  double E_s[kMaxGroups];
+};
+// B[g] = rS_g - S_gg x_g + sum_{h != g} K_gh x_h for every group at once
+// (rS_g null: B[g] = S_gg x_g - sum_{h != g} K_gh x_h, the operator applied
+// to x), with the partial sums of sum_g (B_g / E_s,g)^2 (RS_FE2) and of the
+// same sum over the magnitudes of the terms that make B_g (RS_MAG2: the
+// scale of its rounding error).
+void launch_groups_coupled(hipStream_t s, const StepK& k, int G, const GroupOps& o,
+                           const double* K, const double* x, double* B, double* part);
+// Krylov vectors over [G][N] fields with the inner product
+// <u, v>_W = sum_g w[g] sum_P u v (w[g] = 1 / E_s,g^2, the norm's weights).
+constexpr int kKrylovMax = 12;    // vectors one call combines or dots against
+constexpr int kKrylovGrid = 1024; // workgroups of the Krylov kernels
+struct WeightK {
+  double w[kMaxGroups];
+};
+struct Coefs {
+  double c[kKrylovMax];
+};
+// out[i] = <u, V_i>_W for i < nv (V_i = V + i stride); part: kKrylovMax *
+// kKrylovGrid doubles of scratch; out may be mapped host memory.
+void launch_wdots(hipStream_t s, long long N, int G, const WeightK& wk, const double* u,
+                  const double* V, long long stride, int nv, double* part, double* out);
+// y = a y + sum_{i < nv} c_i V_i (a = 0: y is overwritten); with norm_out,
+// also *norm_out = ||y||_W^2 after the update.
+void launch_wcombine(hipStream_t s, long long N, int G, const WeightK& wk, double* y, double a,
+                     const double* V, long long stride, int nv, const Coefs& c, double* part,
+                     double* norm_out);
 // E_g = frac[g] E0, n_HI = (1 - x0) n_H, with helium n_HeI = (1 - x0) n_He
 // and n_HeII = x0 n_He, e = e0 (e null: isothermal); RS_NONFINITE flags a
 // bad n_H.

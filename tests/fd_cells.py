@@ -12,14 +12,18 @@ moves the state the adjoint linearises about (measured: 1% in the
 gradients of dark cells; 1e-6 with the tight forward).
 
 Step per cell: h_P = eps max(|p_P|, p_bar), p_bar the mean of the nonzero
-entries of p (most cells emit nothing), eps = 1e-6 for src and 1e-4 for
-n_H: a relative change of 1e-6 in one cell's n_H changes J by ~3e-17, at
-the resolution of the forward map in FP64 (measured differences 4e-4), while
-eps = 1e-4 leaves a central-difference truncation of order eps^2.  Central differences, except for
-src in a cell that emits nothing: there a negative step makes E negative in
-that cell, where the photoionisation rate takes max(E, 0); the adjoint
-differentiates at the unperturbed state (E > 0), which the forward
-difference (J(p + h) - J(p)) / h matches.  The difference of J is formed as
+entries of p (most cells emit nothing), eps = 1e-6 for src and 1e-3 for
+n_H.  Central differences, except for src in a cell that emits nothing:
+there a negative step makes E negative in that cell, where the
+photoionisation rate takes max(E, 0); the adjoint differentiates at the
+unperturbed state (E > 0), which a one-sided difference matches.  It is the
+second-order one, (-3 J(p) + 4 J(p + h) - J(p + 2 h)) / (2 h): a new source
+responds nonlinearly, and the first-order difference carries a truncation
+of about 1.4e3 eps (measured in such a cell: 1.4e-3 at eps = 1e-6, falling
+in proportion to eps).  For n_H a relative change of 1e-4 in one cell moves
+J by ~3e-15, near the resolution of the forward map in FP64 (measured
+scatter of the central difference 1e-3 there); eps = 1e-3 leaves a
+truncation of order eps^2.  The difference of J is formed as
 the mean of the cell-by-cell differences of x_HII, so cells the
 perturbation does not reach cancel exactly.  Perturbing n_H also moves the
 initial n_HI = (1 - x0) n_H; T0 is fixed.
@@ -83,7 +87,7 @@ def run(n_cells=64, nsteps=10, dev="cuda:0", log=print, adjoint_params=None):
     x_base = forward(src_h, nH_h)
     cells = W.fd_cells(w)[:n_cells]
     pbar = {"src": float(src_h[src_h > 0].mean()), "nH": float(nH_h.mean())}
-    eps = {"src": 1e-6, "nH": 1e-4}
+    eps = {"src": 1e-6, "nH": 1e-3}
     gmax = {"src": float(np.abs(g_src).max()), "nH": float(np.abs(g_nH).max())}
     results = []
     for c in cells:
@@ -96,8 +100,13 @@ def run(n_cells=64, nsteps=10, dev="cuda:0", log=print, adjoint_params=None):
             args_p = (plus, nH_h) if name == "src" else (src_h, plus)
             xp = forward(*args_p)
             if name == "src" and p == 0.0:
-                fd = float((xp - x_base).sum().item()) / N / h
-                kind = "forward"
+                plus2 = base.copy()
+                plus2[ijk] = p + 2.0 * h
+                xp2 = forward(plus2, nH_h)
+                d1 = float((xp - x_base).sum().item())
+                d2 = float((xp2 - x_base).sum().item())
+                fd = (4.0 * d1 - d2) / N / (2.0 * h)
+                kind = "one-sided"
             else:
                 minus = base.copy()
                 minus[ijk] = p - h

@@ -249,7 +249,7 @@ def test_full_size_adjoint_matches_finite_differences(hip_device):
 def test_adjoint_per_cell_finite_differences_256(hip_device):
     """The 256^3 lognormal volume's adjoint check as the workload states it,
     on a subset: per-cell finite differences (relative steps 1e-6 for src,
-    1e-4 for n_H; see tests/fd_cells.py) of J = mean x_HII with respect to
+    1e-3 for n_H; see tests/fd_cells.py) of J = mean x_HII with respect to
     src and n_H of 4 of the 64 seeded cells, after 3 mixed forward steps (the
     full check runs all 64 cells over 10 steps), to 1e-4."""
     from fd_cells import run

@@ -95,6 +95,8 @@ def test_workspace_grows_with_the_groups():
         sizes.append(_lib.lib.rh_multigroup_workspace_bytes(ctypes.byref(p), ctypes.byref(mg)))
     N = 16 ** 3
     for G, b in zip((1, 2, 3, 4), sizes):
-        # one grey workspace per group plus G^2 + 12 G + 17 coupled fields
-        assert b >= G * grey + (G * G + 12 * G + 17) * 8 * N
-        assert b <= G * (grey + 256) + (G * G + 12 * G + 17) * 8 * N + 15 * 256
+        # one grey workspace per group plus G^2 + 29 G + 17 coupled fields (17 G
+        # of them the Krylov bases) and 12 x 1024 Krylov partial sums
+        fields = (G * G + 29 * G + 17) * 8 * N + 12 * 1024 * 8
+        assert b >= G * grey + fields
+        assert b <= G * (grey + 256) + fields + 18 * 256
