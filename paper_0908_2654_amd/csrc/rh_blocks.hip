@@ -83,65 +83,118 @@ void launch_src_list(hipStream_t s, long long N, long long chunk, int groups, co
 }
 
 // ---------------------------------------------------------------------------
-// box inverses (Gauss-Jordan in LDS, FP64; the box matrix is a principal
+// box inverses (Gauss-Jordan in FP64; the box matrix is a principal
 // submatrix of the symmetric positive definite Schur operator, so no
 // pivoting is needed)
 // ---------------------------------------------------------------------------
+// The 128 x 128 padded matrix is spread over a 16 x 16 grid of threads:
+// thread (r, c) keeps the 64 entries (r + 16 a, c + 16 b), a, b < 8, in
+// registers; a pivot step exchanges only row k and column k through LDS.
 constexpr int kBlockThreads = 256;
-static_assert(kBlockMaxCells <= 128, "one column per thread of a 128-wide row");
+constexpr int kInvTile = 16;                    // thread grid side
+constexpr int kInvPer = 128 / kInvTile;         // rows (columns) per thread
+static_assert(kBlockMaxCells <= 128, "boxes fit the 128 x 128 register tile");
+static_assert(kInvTile * kInvTile == kBlockThreads, "one thread per tile position");
 
 template <class T>
 __global__ void __launch_bounds__(kBlockThreads)
 k_block_inverse(LevelK<T> l, BlockSet<T> bs) {
-  __shared__ double A[kBlockMaxCells * kBlockMaxCells];
-  __shared__ double col[kBlockMaxCells], rowk[kBlockMaxCells];
+  // the box's 7-point rows: diagonal and the six couplings (0 outside the box)
+  __shared__ double coef[kBlockMaxCells][7];
+  __shared__ double rowk[128], colk[128];
   const int m = bs.m;
   const int blk = blockIdx.x;
   const int s0 = bs.start[3 * blk], s1 = bs.start[3 * blk + 1], s2 = bs.start[3 * blk + 2];
-  for (int t = threadIdx.x; t < m * m; t += kBlockThreads) A[t] = 0.0;
-  __syncthreads();
-  // row of local cell p: diagonal and the couplings to the other box cells
+  const int exy = bs.ey * bs.ez;
   for (int p = threadIdx.x; p < m; p += kBlockThreads) {
-    const int lx = p / (bs.ey * bs.ez), ly = (p / bs.ez) % bs.ey, lz = p % bs.ez;
-    const int c[3] = {s0 + lx, s1 + ly, s2 + lz};
-    const long long P = cell_index(c[0], c[1], c[2], l.ny, l.nz);
-    A[p * m + p] = (double)l.diag[P];
-    if (lx + 1 < bs.ex) A[p * m + p + bs.ey * bs.ez] = -(double)l.cf[0][P];
-    if (lx > 0) A[p * m + p - bs.ey * bs.ez] = -(double)l.cf[0][P - (long long)l.ny * l.nz];
-    if (ly + 1 < bs.ey) A[p * m + p + bs.ez] = -(double)l.cf[1][P];
-    if (ly > 0) A[p * m + p - bs.ez] = -(double)l.cf[1][P - l.nz];
-    if (lz + 1 < bs.ez) A[p * m + p + 1] = -(double)l.cf[2][P];
-    if (lz > 0) A[p * m + p - 1] = -(double)l.cf[2][P - 1];
+    const int lx = p / exy, ly = (p / bs.ez) % bs.ey, lz = p % bs.ez;
+    const long long P = cell_index(s0 + lx, s1 + ly, s2 + lz, l.ny, l.nz);
+    coef[p][0] = (double)l.diag[P];
+    coef[p][1] = lx + 1 < bs.ex ? -(double)l.cf[0][P] : 0.0;
+    coef[p][2] = lx > 0 ? -(double)l.cf[0][P - (long long)l.ny * l.nz] : 0.0;
+    coef[p][3] = ly + 1 < bs.ey ? -(double)l.cf[1][P] : 0.0;
+    coef[p][4] = ly > 0 ? -(double)l.cf[1][P - l.nz] : 0.0;
+    coef[p][5] = lz + 1 < bs.ez ? -(double)l.cf[2][P] : 0.0;
+    coef[p][6] = lz > 0 ? -(double)l.cf[2][P - 1] : 0.0;
   }
   __syncthreads();
+  const int r = threadIdx.x / kInvTile, c = threadIdx.x % kInvTile;
+  // entries; rows and columns past m form an identity block (never coupled)
+  double A[kInvPer][kInvPer];
+#pragma unroll
+  for (int a = 0; a < kInvPer; ++a) {
+    const int i = r + kInvTile * a;
+#pragma unroll
+    for (int b = 0; b < kInvPer; ++b) {
+      const int j = c + kInvTile * b;
+      double v = 0.0;
+      if (i >= m || j >= m) {
+        v = i == j ? 1.0 : 0.0;
+      } else {
+        const int d = j - i;
+        if (d == 0) v = coef[i][0];
+        else if (d == exy) v = coef[i][1];
+        else if (d == -exy) v = coef[i][2];
+        else if (d == bs.ez) v = coef[i][3];
+        else if (d == -bs.ez) v = coef[i][4];
+        else if (d == 1) v = coef[i][5];
+        else if (d == -1) v = coef[i][6];
+      }
+      A[a][b] = v;
+    }
+  }
   // in-place Gauss-Jordan: step k divides row k by the pivot, puts 1/pivot
   // in its place and eliminates column k from the other rows (which take
-  // -a_ik / pivot in column k); column k and row k are staged first, so
-  // every update reads values of the previous step
+  // -a_ik / pivot in column k); row k and column k of the previous step are
+  // staged in LDS first
   for (int k = 0; k < m; ++k) {
-    for (int i = threadIdx.x; i < m; i += kBlockThreads) {
-      col[i] = A[i * m + k];
-      rowk[i] = i == k ? 1.0 : A[k * m + i];
-    }
+    const int kr = k % kInvTile, ka = k / kInvTile;
+    // row k and column k to LDS (register indices stay compile-time constants)
+#pragma unroll
+    for (int a = 0; a < kInvPer; ++a)
+      if (a == ka && r == kr) {
+#pragma unroll
+        for (int b = 0; b < kInvPer; ++b) rowk[c + kInvTile * b] = A[a][b];
+      }
+#pragma unroll
+    for (int b = 0; b < kInvPer; ++b)
+      if (b == ka && c == kr) {
+#pragma unroll
+        for (int a = 0; a < kInvPer; ++a) colk[r + kInvTile * a] = A[a][b];
+      }
     __syncthreads();
-    const double inv_piv = 1.0 / col[k];
-    // thread: column j = tid mod 128, rows tid / 128, + 2, + 4, ... (a
-    // wavefront shares its row: col[i] is a broadcast, rowk[j] contiguous)
-    const int j = threadIdx.x & 127;
-    if (j < m) {
-      const double rj = rowk[j] * inv_piv;
-      for (int i = threadIdx.x >> 7; i < m; i += kBlockThreads / 128) {
-        double* a = &A[i * m + j];
-        if (i == k)
-          *a = rj;
+    const double inv_piv = 1.0 / colk[k];
+    double ci[kInvPer], rj[kInvPer];
+#pragma unroll
+    for (int a = 0; a < kInvPer; ++a) ci[a] = colk[r + kInvTile * a];
+#pragma unroll
+    for (int b = 0; b < kInvPer; ++b) rj[b] = rowk[c + kInvTile * b] * inv_piv;
+#pragma unroll
+    for (int a = 0; a < kInvPer; ++a) {
+      const bool rowk_here = r == kr && a == ka;
+#pragma unroll
+      for (int b = 0; b < kInvPer; ++b) {
+        const bool colk_here = c == kr && b == ka;
+        double v;
+        if (rowk_here)
+          v = colk_here ? inv_piv : rj[b];
         else
-          *a = (j == k ? 0.0 : *a) - col[i] * rj;
+          v = (colk_here ? 0.0 : A[a][b]) - ci[a] * (colk_here ? inv_piv : rj[b]);
+        A[a][b] = v;
       }
     }
     __syncthreads();
   }
   T* out = bs.inv + (long long)blk * m * m;
-  for (int t = threadIdx.x; t < m * m; t += kBlockThreads) out[t] = (T)A[t];
+#pragma unroll
+  for (int a = 0; a < kInvPer; ++a) {
+    const int i = r + kInvTile * a;
+#pragma unroll
+    for (int b = 0; b < kInvPer; ++b) {
+      const int j = c + kInvTile * b;
+      if (i < m && j < m) out[i * m + j] = (T)A[a][b];
+    }
+  }
 }
 
 template <class T>
