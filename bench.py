@@ -241,7 +241,8 @@ def cpu_baseline(w, nH_full, state, t, dt, sub=64):
     sub^3 block cut from a checkpoint of the timed window (the GPU state at
     the start of the first timed step: same cells, density, sources, fields,
     time and step), closed as a periodic box; BLAS limited to one thread,
-    which is what NumPy's elementwise work and SciPy's sparse solvers use."""
+    which is what NumPy's elementwise work and SciPy's sparse solvers use.
+    A sample that is the whole grid keeps the workload's walls."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -250,7 +251,8 @@ def cpu_baseline(w, nH_full, state, t, dt, sub=64):
     ws = W.get(w)
     ws.dims = (sub, sub, sub)
     ws.box_comoving_cm = w.box_comoving_cm * sub / w.dims[0]
-    ws.bc = (W.BC_PERIODIC,) * 6
+    if tuple(w.dims) != (sub, sub, sub):
+        ws.bc = (W.BC_PERIODIC,) * 6
     cut = (slice(0, sub),) * 3
     nH = np.ascontiguousarray(nH_full[cut])
     Q = np.ascontiguousarray(W.photon_rate_field(w)[cut])
@@ -271,8 +273,10 @@ def cpu_baseline(w, nH_full, state, t, dt, sub=64):
         "kind": "oracle",
         "sample": f"one implicit step (Newton to ||f|| <= 1e-8, {st['newton_its']} iterations) of a "
                   f"{sub}^3 block of the GPU state at the start of the first timed step (same "
-                  f"density, sources, fields, t and dt; the block closed periodically), "
-                  f"{el:.1f} s on one thread (BLAS limited to 1)",
+                  f"density, sources, fields, t and dt; "
+                  + ("the whole grid" if tuple(w.dims) == (sub, sub, sub)
+                     else "the block closed periodically")
+                  + f"), {el:.1f} s on one thread (BLAS limited to 1)",
         "host": host_description(),
     }
 
@@ -424,6 +428,8 @@ def main():
                     help="0 auto, 1 one launch per colour, 2 fused sweep wherever it fits")
     ap.add_argument("--block-radius", type=int, default=2,
                     help="box radius of the block smoother around sources (0 off)")
+    ap.add_argument("--block-levels", type=int, default=2,
+                    help="multigrid levels with source boxes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--multigroup", action="store_true",
@@ -454,7 +460,7 @@ def main():
         print(json.dumps({"copy_bytes": 4 << 28, "launches": 3}))
         return
     MG.update(mg_pre=args.mg_pre, mg_post=args.mg_post, smoother=args.smoother,
-              mg_block_radius=args.block_radius)
+              mg_block_radius=args.block_radius, mg_block_levels=args.block_levels)
     if args.multigroup:
         print(json.dumps(run_multigroup(args, dev)), flush=True)
         return
@@ -566,8 +572,8 @@ def main():
                    "steps_of_run": f"{args.warmup}..{args.warmup + args.steps - 1} of {nsteps}",
                    "newton_tol": 1e-8, "lin_forcing": 1e-13,
                    "outer": f"PCG, V({args.mg_pre},{args.mg_post}) preconditioner"
-                            + (f", source boxes of radius {args.block_radius} on 2 levels"
-                               if args.block_radius else ""),
+                            + (f", source boxes of radius {args.block_radius} on "
+                               f"{args.block_levels} levels" if args.block_radius else ""),
                    "lin_max_it": 500},
         "per_step": {"newton_its": [x["newton_its"] for x in st_m],
                      "vcycles": [x["lin_its_total"] for x in st_m],

@@ -17,10 +17,10 @@ n_H.  Central differences, except for src in a cell that emits nothing:
 there a negative step makes E negative in that cell, where the
 photoionisation rate takes max(E, 0); the adjoint differentiates at the
 unperturbed state (E > 0), which a one-sided difference matches.  It is the
-second-order one, (-3 J(p) + 4 J(p + h) - J(p + 2 h)) / (2 h): a new source
-responds nonlinearly, and the first-order difference carries a truncation
-of about 1.4e3 eps (measured in such a cell: 1.4e-3 at eps = 1e-6, falling
-in proportion to eps).  For n_H a relative change of 1e-4 in one cell moves
+second-order one, (-3 J(p) + 4 J(p + h) - J(p + 2 h)) / (2 h), with a
+quarter of the step: a new source responds nonlinearly (the first-order
+difference carries a truncation of about 1.4e3 eps in such a cell, the
+second-order one 1.6e-4 at eps = 1e-6, falling as eps^2).  For n_H a relative change of 1e-4 in one cell moves
 J by ~3e-15, near the resolution of the forward map in FP64 (measured
 scatter of the central difference 1e-3 there); eps = 1e-3 leaves a
 truncation of order eps^2.  The difference of J is formed as
@@ -94,12 +94,13 @@ def run(n_cells=64, nsteps=10, dev="cuda:0", log=print, adjoint_params=None):
         ijk = np.unravel_index(int(c), op.dims)
         for name, base, g in (("src", src_h, g_src), ("nH", nH_h, g_nH)):
             p = float(base[ijk])
-            h = eps[name] * max(abs(p), pbar[name])
+            one_sided = name == "src" and p == 0.0
+            h = eps[name] * max(abs(p), pbar[name]) * (0.25 if one_sided else 1.0)
             plus = base.copy()
             plus[ijk] = p + h
             args_p = (plus, nH_h) if name == "src" else (src_h, plus)
             xp = forward(*args_p)
-            if name == "src" and p == 0.0:
+            if one_sided:
                 plus2 = base.copy()
                 plus2[ijk] = p + 2.0 * h
                 xp2 = forward(plus2, nH_h)
