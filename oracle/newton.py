@@ -218,7 +218,8 @@ def solve_spd(S, r):
     1e-14, restarted on the true residual (iterative refinement) while the
     attained residual is above 1e-12 of ||r||, at most three times: on
     ill-conditioned operators the recursively updated CG residual drifts
-    from the true one.
+    from the true one.  The attained residual is accepted down to the
+    rounding floor of its own evaluation, 16 eps || |S| |x| + |r| ||.
     """
     if S.shape[0] <= DIRECT_MAX:
         return spla.spsolve(S.tocsc(), r)
@@ -226,16 +227,23 @@ def solve_spd(S, r):
     if rn == 0.0:
         return np.zeros_like(r)
     Minv = sp.diags(1.0 / S.diagonal())
+    absS = abs(S)
     x = np.zeros_like(r)
+    info = 0
+
+    def accepted(res, x):
+        floor = 16.0 * np.finfo(np.float64).eps * np.linalg.norm(absS @ np.abs(x) + np.abs(r))
+        return res <= max(1e-12 * rn, floor)
+
     for _ in range(4):
         res_vec = r - S @ x
         res = np.linalg.norm(res_vec)
-        if res <= 1e-12 * rn:
+        if accepted(res, x):
             return x
         dx, info = spla.cg(S, res_vec, rtol=1e-14, atol=0.0, maxiter=50000, M=Minv)
         x = x + dx
     res = np.linalg.norm(S @ x - r)
-    if res > 1e-12 * rn:
+    if not accepted(res, x):
         raise NewtonFailure(f"CG residual {res / rn:.2e} (info {info})")
     return x
 
