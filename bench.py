@@ -381,7 +381,8 @@ def run_multigroup(args, dev):
         "config": {"workload": w.name + "_3groups_he", "grid": list(w.dims),
                    "sources": w.n_sources, "group_edges_eV": list(MG_EDGES_EV), "y_he": MG_Y_HE,
                    "newton_tol": 1e-8, "lin_forcing": 1e-13,
-                   "linear": "block Gauss-Seidel over groups, PCG + V(2,2) per group"},
+                   "linear": "FGMRES(8) preconditioned by one block Gauss-Seidel sweep over the "
+                             "groups, each group by PCG + V(2,2)"},
         "per_step": {"newton_its": [x["newton_its"] for x in stats],
                      "multigrid_its": [x["lin_its_total"] for x in stats],
                      "sweeps_max": [x["lin_its_max"] for x in stats],

@@ -37,7 +37,7 @@ def kernels_sha256() -> str:
 
 
 def _short(name: str) -> str:
-    name = name.replace("void ", "").replace("rh::", "")
+    name = name.replace("void ", "").replace("rh::", "").replace("(anonymous namespace)::", "")
     return name.split("(")[0]
 
 
