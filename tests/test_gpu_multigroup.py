@@ -1,8 +1,9 @@
 """GPU parity of the hydrogen + helium multigroup step (rh_multigroup_*)
 against the multigroup oracle (oracle/multigroup.py) on the same seeded
 inputs: initial fields, residuals at perturbed states (elementwise), whole
-steps in FP64 and mixed precision (elementwise), and the one-group,
-hydrogen-only limit against the grey GPU step."""
+steps in FP64 and mixed precision (elementwise), the one-group,
+hydrogen-only limit against the grey GPU step, and one step of the 128^3
+volume checked at sampled cells."""
 import numpy as np
 import pytest
 
@@ -242,3 +243,89 @@ def test_step_restores_state_on_failure_and_rejects_bad_arguments(hip_device):
         s.step(inp["t0"], -1.0, nH, src, E, e, y)
     assert ex.value.status == _lib.RH_EINVAL
     s.close()
+
+
+def test_full_size_multigroup_step_sampled(hip_device):
+    """The 128^3 lognormal volume (32 sources, periodic) with three groups and
+    helium, in the configuration bench.py --multigroup times (mixed
+    precision, FGMRES around the block sweep): one GPU step, then at sampled
+    cells (source cells, the most ionised cells, random cells) the oracle
+    evaluates on a periodic 3^3 block around the cell (a cell's residual
+    needs only its face neighbours; the limiter floor is the whole box's)
+    the residual of the GPU's solution, which rh_multigroup_residual also
+    evaluated for the whole grid."""
+    w = W.get(2)
+    mp = MG.params_from_workload(w, EDGES3, 0.08)
+    nH = W.density_field(w)
+    src = OM.source_field(mp.base, W.photon_rate_field(w))
+    t0, dt, _ = OM.schedule(mp.base, w)
+    E0, e0, y0 = MG.initial_state(mp, nH, w.x0, w.T0, w.E0)
+    s = _solver(w, mp, hip_device, precision=1)
+    d = lambda a: to_dev(a, hip_device)  # noqa: E731
+    nHd, srcd = d(nH), d(src)
+    Un = (d(E0), d(e0), d(y0))
+    U = tuple(x.clone() for x in Un)
+    st = s.step(t0, dt, nHd, srcd, *U)
+    print("step", {k: st[k] for k in ("newton_its", "lin_its_total", "lin_its_max", "res_final")})
+    assert st["lin_cap_hits"] == 0
+    gE, ge, gy, gnorm = s.residual(t0, dt, nHd, srcd, Un, U)
+    s.close()
+    assert gnorm <= w.newton_tol and gnorm == pytest.approx(st["res_final"], rel=1e-6)
+    U1 = tuple(x.cpu().numpy() for x in U)
+    g = (gE.cpu().numpy(), ge.cpu().numpy(), gy.cpu().numpy())
+    worst, sampled, cells = sampled_check(w, mp, nH, src, t0, dt, (E0, e0, y0), U1, g)
+    print("cells", len(cells), "parity", worst, "oracle residual at sampled cells", sampled)
+    assert worst["fE"] < 1e-12 and worst["fy"] < 1e-12 and worst["fe"] < 1e-12
+    assert sampled["fE"] < 1e-5 and sampled["fy"] < 1e-5 and sampled["fe"] < 1e-5
+
+
+def sampled_check(w, mp, nH, src, t0, dt, Un, U1, g):
+    """Largest differences between the residual g = (fE, fe, fy) of state U1
+    (step from Un) and the oracle's, at sampled cells each on a periodic
+    3^3 block, relative to the size of the terms; and the oracle's residual
+    there.  Returns (worst, sampled, cells)."""
+    import dataclasses
+
+    from oracle.constants import C_LIGHT
+    E0, e0, y0 = Un
+    E1, e1, y1 = U1
+    gE, ge, gy = g
+    dims = w.dims
+    rng = np.random.default_rng(5)
+    cells = [tuple(int(v) for v in c) for c in np.argwhere(src > 0)[:16]]
+    x1 = 1.0 - y1[0] / nH
+    top = np.argpartition(x1.ravel(), -64)[-64:]
+    cells += [tuple(int(v) for v in np.unravel_index(i, dims)) for i in rng.choice(top, 16, replace=False)]
+    cells += [tuple(int(rng.integers(0, n)) for n in dims) for _ in range(24)]
+    a_n = mp.base.cosmo.a(t0)
+    bp = mp.base.with_(dims=(3, 3, 3), box=3 * mp.base.h, R_min=1.0 / (a_n * mp.base.box),
+                       bc=(1,) * 6)
+    mpb = dataclasses.replace(mp, base=bp)
+    srcg = np.stack([f * src for f in mp.groups["frac"]])
+    E_s = [max(float(E0[g].max()), dt * float(srcg[g].max()), bp.E_floor) for g in range(mp.G)]
+    nHe_all = mp.y_he * nH
+    ctr = (1, 1, 1)
+    worst = {"fE": 0.0, "fy": 0.0, "fe": 0.0}
+    sampled = {"fE": 0.0, "fy": 0.0, "fe": 0.0}
+    for c in cells:
+        idx = [np.arange(c[k] - 1, c[k] + 2) % dims[k] for k in range(3)]
+        cut = lambda X: X[np.ix_(*idx)]  # noqa: E731
+        cutg = lambda X: np.stack([cut(X[g]) for g in range(X.shape[0])])  # noqa: E731
+        ctx = MG.make_context(mpb, t0, dt, cut(nH), cut(src), cutg(E0), cut(e0), cutg(y0))
+        Eb, eb, yb = cutg(E1), cut(e1), cutg(y1)
+        fEo, feo, fyo = MG.residual(mpb, ctx, Eb, eb, yb)
+        kap = MG.opacity(mpb, yb, ctx.a_1)
+        for g in range(mp.G):
+            cfs = sum(ctx.cf_1[g][a][ctr] + ctx.cf_1[g][a][tuple(2 if b == a else 1 for b in range(3))]
+                      for a in range(3))
+            scale = np.abs(Eb[g]).max() * (1.0 + dt * cfs) + abs(ctx.En[g][ctr]) \
+                + dt * ctx.src[g][ctr] + dt * C_LIGHT * kap[g][ctr] * abs(Eb[g][ctr])
+            worst["fE"] = max(worst["fE"], abs(gE[g][c] - fEo[g][ctr]) / scale)
+            sampled["fE"] = max(sampled["fE"], abs(fEo[g][ctr]) / E_s[g])
+        nHe = nHe_all[c]
+        for sp_, ref in ((0, nH[c]), (1, nHe), (2, nHe)):
+            worst["fy"] = max(worst["fy"], abs(gy[sp_][c] - fyo[sp_][ctr]) / ref)
+            sampled["fy"] = max(sampled["fy"], abs(fyo[sp_][ctr]) / ref)
+        worst["fe"] = max(worst["fe"], abs(ge[c] - feo[ctr]) / eb[ctr])
+        sampled["fe"] = max(sampled["fe"], abs(feo[ctr]) / ctx.en[ctr])
+    return worst, sampled, cells
