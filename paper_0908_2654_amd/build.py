@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["csrc/rh_kernels.hip", "csrc/rh_advect.hip", "csrc/rh_blocks.hip", "csrc/rh_noalloc.hip",
            "csrc/rh_groups.hip",
-           "csrc/rh_host.cpp"]
+           "csrc/rh_host.cpp", "csrc/rh_groups_host.cpp"]
 LIB = os.path.join(PKG, "librh.so")
 ARCH = os.environ.get("RH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
