@@ -11,18 +11,8 @@
 namespace rh {
 
 __device__ inline void cell_ijk(long long idx, int ny, int nz, int& i, int& j, int& k) {
-  const long long nyz = (long long)ny * nz;
-  if (idx < (1LL << 31) && nyz < (1LL << 31)) {
-    // 32-bit division (every grid here): a fraction of the 64-bit sequence
-    const int c = (int)idx, p = (int)nyz;
-    i = c / p;
-    const int jk = c - i * p;
-    j = jk / nz;
-    k = jk - j * nz;
-    return;
-  }
-  const long long jk = idx % nyz;
-  i = (int)(idx / nyz);
+  long long jk = idx % ((long long)ny * nz);
+  i = (int)(idx / ((long long)ny * nz));
   j = (int)(jk / nz);
   k = (int)(jk % nz);
 }
