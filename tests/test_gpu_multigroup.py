@@ -182,6 +182,20 @@ def test_step_parity_fp64(hip_device, name):
     assert all(s["lin_cap_hits"] == 0 for s in st)
 
 
+@pytest.mark.parametrize("name", ["he3_lognormal", "he2_iso"])
+def test_step_parity_defect_correction(hip_device, name):
+    """Each group's inner solve by plain FP64 defect correction around the
+    V-cycle (krylov = 0) instead of conjugate gradients."""
+    w, mp, inp = _setup(name, newton_tol=1e-12)
+    o = _oracle_traj(name, mp, inp, 1e-12)
+    g, st = _gpu_traj(name, w, mp, inp, hip_device, newton_tol=1e-12, precision=0, krylov=0)
+    err = _traj_errors(g, o, mp, inp["nH"])
+    print(name, "defect correction", {k: f"{v:.1e}" for k, v in err.items()},
+          [(s["newton_its"], s["lin_its_total"], s["lin_its_max"]) for s in st])
+    assert max(err.values()) < 1e-10
+    assert all(s["lin_cap_hits"] == 0 for s in st)
+
+
 @pytest.mark.parametrize("name", ["he3_lognormal", "he4_eds", "he3_lcdm"])
 def test_step_parity_mixed(hip_device, name):
     w, mp, inp = _setup(name, newton_tol=1e-12)
