@@ -53,13 +53,15 @@ void gauss_legendre(int n, double* x, double* w) {
 // int_lo^hi x^m (xs / x)^q / (e^x - 1) dx (hi may be infinite) by composite
 // 20-point Gauss-Legendre panels of width 1/4; the integrand falls as
 // x^m e^-x, so 120 units past lo it no longer contributes in FP64.
+struct GaussLegendre20 {
+  double x[20], w[20];
+  GaussLegendre20() { gauss_legendre(20, x, w); }
+};
+
 double bose_moment(double lo, double hi, int m, double xs, double q) {
-  static double gx[20], gw[20];
-  static bool ready = false;
-  if (!ready) {
-    gauss_legendre(20, gx, gw);
-    ready = true;
-  }
+  static const GaussLegendre20 gl;  // initialised once, thread-safe
+  const double* gx = gl.x;
+  const double* gw = gl.w;
   const double top = std::min(hi, lo + 120.0);
   if (!(top > lo)) return 0.0;
   const int panels = std::max(1, (int)std::ceil((top - lo) / 0.25));
@@ -251,7 +253,8 @@ rh_status groups_setup(rh_multigroup* h, StepK (&kg)[kMaxGroups], double t_n, do
   for (int g = 0; g < h->G; ++g) {
     kg[g] = group_step(h, g, t_n, dt);
     rh_status st = handle_setup_step(h->sub[g], kg[g], src, h->En + g * h->N, h->yn,
-                              h->he ? h->yn + h->N : nullptr, h->he ? h->yn + 2 * h->N : nullptr);
+                                     h->he ? h->yn + h->N : nullptr,
+                                     h->he ? h->yn + 2 * h->N : nullptr);
     if (st != RH_OK) return sub_fail(h, g, st);
   }
   return RH_OK;
