@@ -151,7 +151,10 @@ typedef struct rh_step_stats {
                                /* 4 V-cycles; 5 the outer linear iteration (conjugate-   */
                                /* gradient or defect-correction kernels and their        */
                                /* reductions).  Host latency between launches counts in  */
-                               /* the phase it interrupts.  [6], [7] are 0.              */
+                               /* the phase it interrupts.  [6], [7] are 0.  The same    */
+                               /* phases are ROCTx ranges (host time, enqueues + waits)  */
+                               /* inside one range per call, for a profiler's marker     */
+                               /* trace.                                                 */
   int32_t lin_cap_hits;        /* linear solves that stopped without reaching their      */
                                /* target (at lin_max_it, on stagnation or breakdown)     */
   int32_t lin_its_max;         /* most V-cycles in one linear solve of the call          */

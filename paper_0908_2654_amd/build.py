@@ -19,6 +19,8 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc"),
          # no packed FP32 instructions in any device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# ROCTx: the library marks its step phases as profiler ranges
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _run(cmd):
@@ -41,7 +43,7 @@ def build(verbose: bool = False) -> str:
             print(out)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LINK, "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

@@ -246,6 +246,7 @@ StepK group_step(const rh_multigroup* h, int g, double t_n, double dt) {
 // the constant part of the residual, E_s and the coarse coefficients.
 rh_status groups_setup(rh_multigroup* h, StepK (&kg)[kMaxGroups], double t_n, double dt,
                        const double* src, const double* E, const double* e, const double* y) {
+  MarkerRange mark("groups: step setup");
   const size_t f = sizeof(double) * h->N;
   GHIPCHK(hipMemcpyAsync(h->En, E, f * h->G, hipMemcpyDeviceToDevice, h->stream));
   if (!h->iso) GHIPCHK(hipMemcpyAsync(h->en, e, f, hipMemcpyDeviceToDevice, h->stream));
@@ -266,6 +267,7 @@ rh_status groups_eval(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const GSt
                       const double* dE, double lam, const GState& out, bool predictor,
                       const double* nH, int mode, double* fE, double* fe, double* fy,
                       GEval& res) {
+  MarkerRange mark("groups: local solve + residuals");
   const long long N = h->N;
   rh_handle* s0 = h->sub[0];
   GroupLocalArgs a{};
@@ -360,6 +362,10 @@ rh_status groups_precondition(rh_multigroup* h, const StepK (&kg)[kMaxGroups], c
     rh_status st = coupled_residual(h, kg[g], g, v + g * N, z, fe2, rmax);
     if (st != RH_OK) return st;
     if (rmax == 0.0) continue;
+    static_assert(kMaxGroups == 4, "one range name per group");
+    static const char* const kInner[kMaxGroups] = {"group 1 inner solve", "group 2 inner solve",
+                                                   "group 3 inner solve", "group 4 inner solve"};
+    MarkerRange mark(kInner[g]);
     rh_handle* s = h->sub[g];
     const double wsub = std::sqrt(fe2 / (N * handle_nvars(s)));
     double* keep = s->rS;
@@ -390,6 +396,7 @@ rh_status groups_precondition(rh_multigroup* h, const StepK (&kg)[kMaxGroups], c
 rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double target,
                        int max_sweeps, int& its_total, int& sweeps, bool& reached,
                        double& w_final) {
+  MarkerRange mark("groups: FGMRES");
   const long long N = h->N;
   const int G = h->G;
   const long long GN = (long long)G * N;
@@ -678,6 +685,7 @@ rh_status rh_multigroup_step(rh_multigroup* h, double t_n, double dt, const doub
   if (!h) return RH_EINVAL;
   rh_status st = groups_args(h, t_n, dt, nH, src, E, e, y);
   if (st != RH_OK) return st;
+  MarkerRange mark("rh_multigroup_step");
   h->local_its_max = 0;
   GHIPCHK(hipEventRecord(h->ev0, h->stream));
   StepK kg[kMaxGroups];

@@ -433,7 +433,28 @@ void phase_begin(rh_handle* h) {
   h->phases_on = h->phase_events;
 }
 
+const char* const kPhaseName[6] = {"", "step setup", "local solve + residual",
+                                   "coarse operators", "V-cycles", "outer iteration"};
+
+// The step's profiler ranges: one over the call, and one per phase that
+// phase_mark switches; the destructor closes both on every return path.
+struct StepMarks {
+  rh_handle* h;
+  MarkerRange step;
+  StepMarks(rh_handle* hh, const char* name) : h(hh), step(name) { h->mark_on = true; }
+  ~StepMarks() {
+    if (h->mark_phase) roctxRangeStop(h->mark_id);
+    h->mark_phase = 0;
+    h->mark_on = false;
+  }
+};
+
 void phase_mark(rh_handle* h, int phase) {
+  if (h->mark_on && h->mark_phase != phase) {
+    if (h->mark_phase) roctxRangeStop(h->mark_id);
+    h->mark_id = roctxRangeStartA(kPhaseName[phase]);
+    h->mark_phase = phase;
+  }
   if (!h->phases_on || h->cur_phase == phase || h->npev == rh_handle::kPhaseEv) return;
   if (hipEventRecord(h->pev[h->npev], h->stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -1220,6 +1241,7 @@ rh_status rh_implicit_step(rh_handle* h, double t_n, double dt, const double* nH
   h->lin_res_max = 0.0;
   h->lin_cap_hits = 0;
   h->lin_its_max = 0;
+  StepMarks marks(h, "rh_implicit_step");
   HIPCHK(hipEventRecord(h->ev0, h->stream));
   phase_begin(h);
   phase_mark(h, PH_SETUP);
@@ -1577,6 +1599,7 @@ rh_status rh_adjoint_step(rh_handle* h, double t_n, double dt, const double* nH,
     return fail(h, RH_EINVAL, "expanding cosmology needs t > 0");
   h->lin_its = 0;
   h->local_its_max = 0;
+  StepMarks marks(h, "rh_adjoint_step");
   HIPCHK(hipEventRecord(h->ev0, h->stream));
   phase_begin(h);
   phase_mark(h, PH_SETUP);

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
@@ -98,6 +99,10 @@ struct rh_handle {
   int npev = 0, cur_phase = -1;
   bool phases_on = false, phase_events = false;
   double pms[8] = {};
+  // profiler range (ROCTx) of the current phase, open while a step runs
+  bool mark_on = false;
+  int mark_phase = 0;
+  roctx_range_id_t mark_id = 0;
   // statistics of the current call
   int lin_its, local_its_max, lin_cap_hits, lin_its_max;
   double last_E_s = 1.0;  // E_s of the last step set up (weight of E in the norms)
@@ -111,6 +116,16 @@ struct rh_handle {
 };
 
 namespace rh {
+
+// A named profiler range (ROCTx) over a scope, shown by a marker trace of a
+// profiler; with no profiler attached a call costs one indirect branch.
+struct MarkerRange {
+  roctx_range_id_t id;
+  explicit MarkerRange(const char* name) : id(roctxRangeStartA(name)) {}
+  ~MarkerRange() { roctxRangeStop(id); }
+  MarkerRange(const MarkerRange&) = delete;
+  MarkerRange& operator=(const MarkerRange&) = delete;
+};
 
 // The per-step scalars of a step on handle h (its grey constants).
 StepK handle_step(const rh_handle* h, double t_n, double dt);

@@ -1,9 +1,13 @@
 """Turn rocprofv3 CSV output into the short summaries kept under profiles/.
 
-Two subcommands (no GPU needed; they only read CSV files):
+Three subcommands (no GPU needed; they only read CSV files):
 
   stats    kernel_stats.csv of a ``rocprofv3 --kernel-trace --stats`` run
            -> markdown table (calls, average and total time, share)
+  markers  marker_api_stats.csv of a ``rocprofv3 --marker-trace --stats``
+           run -> markdown table of the library's ROCTx ranges (host time
+           from a range's start to its end: the enqueues of a phase plus
+           the waits for the GPU inside it)
   traffic  counter_collection.csv of two ``--pmc FETCH_SIZE`` /
            ``--pmc WRITE_SIZE`` runs of the benchmark and of the plain
            copy (``bench.py --copy-calibration``) -> JSON record of HBM
@@ -50,6 +54,16 @@ def stats_table(path: str, top: int = 25) -> str:
         tot = float(r["TotalDurationNs"])
         out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
                    f"{tot / 1e6:.1f} | {100 * tot / total:.1f} |")
+    return "\n".join(out)
+
+
+def markers_table(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| range | calls | average ms | total ms |", "|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {r['Name']} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
     return "\n".join(out)
 
 
@@ -105,6 +119,8 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--top", type=int, default=25)
+    m = sub.add_parser("markers")
+    m.add_argument("csv")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -120,6 +136,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_table(a.csv, a.top))
+        return 0
+    if a.cmd == "markers":
+        print(markers_table(a.csv))
         return 0
     rec = traffic_record(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.kind,
                          a.workload, a.cells, a.algorithmic, a.command)
