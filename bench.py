@@ -26,20 +26,27 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per fine cell of one launch of each kernel class
 # (every input field read once, every output written once; halo re-reads
-# and cache effects count zero).  T = 4 (mixed) or 8 (FP64) bytes.
+# and cache effects count zero).  T = 4 (mixed) or 8 (FP64) bytes per
+# multigrid value; F = the bytes of a multigrid face coefficient (bfloat16
+# on FP32 levels, double on FP64 levels).
+def face_bytes(T):
+    return 2 if T == 4 else T
+
+
 def algorithmic_bytes_per_cell(kind, T, iso=False):
+    F = face_bytes(T)
     return {
         # one full red-black sweep in one launch: x, b, diag and the three
         # + face arrays read, the new x written
-        "rbgs_fine": 7 * T,
+        "rbgs_fine": 4 * T + 3 * F,
         # one colour of a sweep: other-colour x, own b and diag, all three
         # + face arrays (own + faces and the neighbours' - faces), own x written
-        "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * T + 0.5 * T,
+        "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * F + 0.5 * T,
         # the V-cycle's last sweep, which also reads r and q for z.r, z.q
-        "rbgs_fine_dots": 7 * T + 2 * 8,
+        "rbgs_fine_dots": 4 * T + 3 * F + 2 * 8,
         # residual fused with the restriction (x, b, diag, 3 faces in; coarse
         # right-hand side out), as the benchmark sizes run it
-        "mg_residual_fine": 6 * T + T / 8,
+        "mg_residual_fine": 3 * T + 3 * F + T / 8,
         "restrict_fine": T + T / 8,
         "prolong_fine": T / 8 + 2 * T,
         # zT, p, x, diag, 3 cf in; p, q, x out (x += alpha p of the previous
@@ -49,7 +56,7 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
         "pcg_precond": T + 2 * 8,           # zT, r, q in (dot products only)
         "residual_schur": 8 * 8 + 2 * 8 + (T if T == 4 else 0),
         "local_solve": (12 if not iso else 8) * 8 + (7 if not iso else 4) * 8,
-        "step_setup": 3 * 8 + 3 * 8 + (3 * 4 if T == 4 else 0) + 8,
+        "step_setup": 3 * 8 + 3 * 8 + (3 * F if T == 4 else 0) + 8,
     }.get(kind)
 
 

@@ -291,7 +291,7 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
       L.b = cv.take<float>(n);
       L.r = cv.take<float>(n);
       L.diag = cv.take<float>(n);
-      for (int a = 0; a < 3; ++a) L.cf[a] = cv.take<float>(n);
+      for (int a = 0; a < 3; ++a) L.cf[a] = cv.take<face_t<float>>(n);
     } else {
       LevelK<double>& L = h->L64[l];
       L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
@@ -517,7 +517,7 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src, const double* En
                      const double* y2n = nullptr) {
   const bool mixed = h->p.precision == RH_PREC_MIXED;
   phase_mark(h, PH_SETUP);
-  float* c32[3] = {nullptr, nullptr, nullptr};
+  face_t<float>* c32[3] = {nullptr, nullptr, nullptr};
   if (mixed)
     for (int a = 0; a < 3; ++a) c32[a] = h->L32[0].cf[a];
   {
@@ -533,14 +533,10 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src, const double* En
   h->last_E_s = k.E_s;
   // coarse face coefficients
   for (int l = 1; l < h->plan.nlev; ++l) {
-    const int* fd = h->plan.dims[l - 1];
-    if (mixed) {
-      const float* f[3] = {h->L32[l - 1].cf[0], h->L32[l - 1].cf[1], h->L32[l - 1].cf[2]};
-      launch_coarsen_faces<float, float>(h->stream, fd[0], fd[1], fd[2], f, h->L32[l]);
-    } else {
-      const double* f[3] = {h->L64[l - 1].cf[0], h->L64[l - 1].cf[1], h->L64[l - 1].cf[2]};
-      launch_coarsen_faces<double, double>(h->stream, fd[0], fd[1], fd[2], f, h->L64[l]);
-    }
+    if (mixed)
+      launch_coarsen_faces<float>(h->stream, h->L32[l - 1], h->L32[l]);
+    else
+      launch_coarsen_faces<double>(h->stream, h->L64[l - 1], h->L64[l]);
     HIPCHK(hipGetLastError());
   }
   return plan_blocks(h, src);

@@ -52,6 +52,55 @@ struct StepK {
   double src_frac;
 };
 
+// Face coefficients of a multigrid level: FP64 levels hold them in double,
+// FP32 levels in bfloat16 (the upper 16 bits of an FP32 pattern, rounded to
+// nearest even).  An FP32 level's diagonal is formed from its rounded faces
+// plus the exact shift, so the stored operator stays a symmetric M-matrix
+// whose energy differs from the exact one's by at most a factor 1 +- 2^-8
+// (every face and the shift enter the energy with non-negative weight).
+template <class T>
+struct FaceOf {
+  using type = T;
+};
+template <>
+struct FaceOf<float> {
+  using type = uint16_t;
+};
+template <class T>
+using face_t = typename FaceOf<T>::type;
+
+__host__ __device__ inline float bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, sizeof f);
+  return f;
+}
+__host__ __device__ inline uint16_t bf16_round(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, sizeof u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+// A face value as a level of type T reads it / stores it.
+template <class T>
+__host__ __device__ inline T face_at(const T* c, long long i) {
+  return c[i];
+}
+__host__ __device__ inline float face_at(const uint16_t* c, long long i) {
+  return bf16_value(c[i]);
+}
+__host__ __device__ inline void face_put(double* c, long long i, double v) { c[i] = v; }
+__host__ __device__ inline void face_put(uint16_t* c, long long i, double v) {
+  c[i] = bf16_round((float)v);
+}
+// A face in its stored form -> its value.
+__host__ __device__ inline float face_value(uint16_t h) { return bf16_value(h); }
+__host__ __device__ inline double face_value(double v) { return v; }
+// The value an FP32 level holds for the face v.
+__host__ __device__ inline double face_rounded(double v) {
+  return (double)bf16_value(bf16_round((float)v));
+}
+
 // One multigrid level (T = float or double).
 template <class T>
 struct LevelK {
@@ -63,7 +112,7 @@ struct LevelK {
   T* b;                 // right-hand side
   T* r;                 // residual scratch
   T* diag;              // diagonal of the Schur operator
-  T* cf[3];             // + face coefficients (dimensionless, 0 on a non-periodic last face)
+  face_t<T>* cf[3];     // + face coefficients (dimensionless, 0 on a non-periodic last face)
 };
 
 // Source-centred boxes of one multigrid level for the block smoother
@@ -134,7 +183,7 @@ void launch_scale_field(hipStream_t s, long long N, double scale, const double* 
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* y1n, const double* y2n,
                        const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
-                       float* cf32_x, float* cf32_y, float* cf32_z, double* rhsn,
+                       uint16_t* cf32_x, uint16_t* cf32_y, uint16_t* cf32_z, double* rhsn,
                        double* part);
 
 // mode 0: solve the local equations at E = E_k + lam dE (dE may be null);
@@ -170,9 +219,8 @@ void launch_residual(hipStream_t s, const StepK& k, const ResidArgs& a, double* 
 // Reduces the slots whose bits are set in mask (bit s = slot s) into out[s].
 void launch_finalize(hipStream_t s, const double* part, double* out, unsigned mask);
 
-template <class Tin, class Tout>
-void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],
-                          const LevelK<Tout>& c);
+template <class T>
+void launch_coarsen_faces(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
 template <class T>
 void launch_coarse_diag(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c);
 template <class T>

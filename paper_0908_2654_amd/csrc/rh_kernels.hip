@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(kBlock)
 k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ nn,
              const double* __restrict__ y1n, const double* __restrict__ y2n,
              const double* __restrict__ src, double* __restrict__ cfx, double* __restrict__ cfy,
-             double* __restrict__ cfz, float* __restrict__ c32x, float* __restrict__ c32y,
-             float* __restrict__ c32z, double* __restrict__ rhsn, double* __restrict__ part) {
+             double* __restrict__ cfz, uint16_t* __restrict__ c32x, uint16_t* __restrict__ c32y,
+             uint16_t* __restrict__ c32z, double* __restrict__ rhsn, double* __restrict__ part) {
   const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
                       k.bc[4] == RH_BC_PERIODIC};
   const int n[3] = {k.nx, k.ny, k.nz};
@@ -65,7 +65,7 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
   };
   double emax = 0.0, smax = 0.0, bad = 0.0;
   double* cfo[3] = {cfx, cfy, cfz};
-  float* c32[3] = {c32x, c32y, c32z};
+  uint16_t* c32[3] = {c32x, c32y, c32z};  // faces of the FP32 finest level (may be null)
   // blocks of one XCD take consecutive cells, so the y neighbours a block
   // reads were loaded by its neighbours on the same XCD (shared L2)
   for (long long idx = xcd_tile(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x;
@@ -90,7 +90,7 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
         Ln += cfp * (EQ - EP);
       }
       cfo[d][idx] = cfp;
-      if (c32[d]) c32[d][idx] = (float)cfp;
+      if (c32[d]) face_put(c32[d], idx, cfp);
       if (k.theta_lt1 && neighbour(c, n, per, d, -1, q)) {
         long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         double EQ = En[Q];
@@ -115,8 +115,8 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
 
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* y1n, const double* y2n, const double* src, double* cfx,
-                       double* cfy, double* cfz, float* c32x, float* c32y, float* c32z,
-                       double* rhsn, double* part) {
+                       double* cfy, double* cfz, uint16_t* c32x, uint16_t* c32y,
+                       uint16_t* c32z, double* rhsn, double* part) {
   hipLaunchKernelGGL(k_step_setup, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, En, nn, y1n, y2n,
                      src, cfx, cfy, cfz, c32x, c32y, c32z, rhsn, part);
 }
@@ -412,6 +412,7 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
     const double EP = a.E[idx];
     const double nP = a.n[idx];
     double LE = 0.0, csum = 0.0;
+    double csum32 = 0.0;  // the same faces as the FP32 finest level holds them
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int q[3];
@@ -419,12 +420,14 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
         const double cf = a.cf[d][idx];
         LE += cf * (a.E[cell_index(q[0], q[1], q[2], k.ny, k.nz)] - EP);
         csum += cf;
+        if (a.diag32) csum32 += face_rounded(cf);
       }
       if (neighbour(c, nd, per, d, -1, q)) {
         const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         const double cf = a.cf[d][Q];
         LE += cf * (a.E[Q] - EP);
         csum += cf;
+        if (a.diag32) csum32 += face_rounded(cf);
       }
     }
     bool bnd = (c[0] == 0 || c[0] == k.nx - 1 || c[1] == 0 || c[1] == k.ny - 1 || c[2] == 0 ||
@@ -450,7 +453,8 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
     }
     if (a.rS) a.rS[idx] = rS;
     if (a.diag64) a.diag64[idx] = diag;
-    if (a.diag32) a.diag32[idx] = (float)diag;
+    // FP32 level: its rounded faces plus the exact shift (diag - csum)
+    if (a.diag32) a.diag32[idx] = (float)((diag - csum) + csum32);
     if (a.fE_out) a.fE_out[idx] = fE;
     sfe += (fE / k.E_s) * (fE / k.E_s);
     rmax = fmax(rmax, fabs(rS));
@@ -585,10 +589,10 @@ void launch_finalize(hipStream_t s, const double* part, double* out, unsigned ma
 // ---------------------------------------------------------------------------
 // multigrid: coarse operators
 // ---------------------------------------------------------------------------
-template <class Tin, class Tout>
+template <class T>
 __global__ void __launch_bounds__(kBlock)
-k_coarsen_faces(int fnx, int fny, int fnz, const Tin* __restrict__ fx, const Tin* __restrict__ fy,
-                const Tin* __restrict__ fz, LevelK<Tout> c) {
+k_coarsen_faces(int fny, int fnz, const face_t<T>* __restrict__ fx,
+                const face_t<T>* __restrict__ fy, const face_t<T>* __restrict__ fz, LevelK<T> c) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
        idx += (long long)blockDim.x * gridDim.x) {
     int I, J, K;
@@ -597,22 +601,21 @@ k_coarsen_faces(int fnx, int fny, int fnz, const Tin* __restrict__ fx, const Tin
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
-        sx += (double)fx[cell_index(2 * I + 1, 2 * J + a, 2 * K + b, fny, fnz)];
-        sy += (double)fy[cell_index(2 * I + a, 2 * J + 1, 2 * K + b, fny, fnz)];
-        sz += (double)fz[cell_index(2 * I + a, 2 * J + b, 2 * K + 1, fny, fnz)];
+        sx += (double)face_at(fx, cell_index(2 * I + 1, 2 * J + a, 2 * K + b, fny, fnz));
+        sy += (double)face_at(fy, cell_index(2 * I + a, 2 * J + 1, 2 * K + b, fny, fnz));
+        sz += (double)face_at(fz, cell_index(2 * I + a, 2 * J + b, 2 * K + 1, fny, fnz));
       }
     // mean of the 4 fine faces, times 1/4 for the doubled cell width
-    c.cf[0][idx] = (Tout)(0.0625 * sx);
-    c.cf[1][idx] = (Tout)(0.0625 * sy);
-    c.cf[2][idx] = (Tout)(0.0625 * sz);
+    face_put(c.cf[0], idx, 0.0625 * sx);
+    face_put(c.cf[1], idx, 0.0625 * sy);
+    face_put(c.cf[2], idx, 0.0625 * sz);
   }
 }
 
-template <class Tin, class Tout>
-void launch_coarsen_faces(hipStream_t s, int fnx, int fny, int fnz, const Tin* const fcf[3],
-                          const LevelK<Tout>& c) {
-  hipLaunchKernelGGL((k_coarsen_faces<Tin, Tout>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, fnx,
-                     fny, fnz, fcf[0], fcf[1], fcf[2], c);
+template <class T>
+void launch_coarsen_faces(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
+  hipLaunchKernelGGL((k_coarsen_faces<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f.ny, f.nz,
+                     f.cf[0], f.cf[1], f.cf[2], c);
 }
 
 // Sum of a cell's interior face coefficients (6 faces).
@@ -623,9 +626,9 @@ __device__ inline double face_sum(const LevelK<T>& l, const int (&c)[3], long lo
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     int q[3];
-    if (neighbour(c, n, l.per, d, +1, q)) s += (double)l.cf[d][idx];
+    if (neighbour(c, n, l.per, d, +1, q)) s += (double)face_at(l.cf[d], idx);
     if (neighbour(c, n, l.per, d, -1, q))
-      s += (double)l.cf[d][cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+      s += (double)face_at(l.cf[d], cell_index(q[0], q[1], q[2], l.ny, l.nz));
   }
   return s;
 }
@@ -675,11 +678,11 @@ __global__ void __launch_bounds__(1024) k_coarsest_inverse(LevelK<T> c, double* 
         int q[3];
         if (neighbour(C, nd, c.per, d, +1, q)) {
           int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
-          A[(long long)P * n + Q] -= (double)c.cf[d][P];
+          A[(long long)P * n + Q] -= (double)face_at(c.cf[d], P);
         }
         if (neighbour(C, nd, c.per, d, -1, q)) {
           int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
-          A[(long long)P * n + Q] -= (double)c.cf[d][Q];
+          A[(long long)P * n + Q] -= (double)face_at(c.cf[d], Q);
         }
       }
     }
@@ -743,10 +746,10 @@ __device__ inline T offdiag_sum(const LevelK<T>& l, const int (&c)[3], long long
   for (int d = 0; d < 3; ++d) {
     int q[3];
     if (neighbour(c, n, l.per, d, +1, q))
-      s += l.cf[d][idx] * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+      s += face_at(l.cf[d], idx) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
     if (neighbour(c, n, l.per, d, -1, q)) {
       long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
-      s += l.cf[d][Q] * l.x[Q];
+      s += face_at(l.cf[d], Q) * l.x[Q];
     }
   }
   return s;
@@ -878,9 +881,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
     const int t = tid + j * NT;
     coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
   }
+  // faces stay in their stored form (bfloat16 bits on FP32 levels) until
+  // they are staged, so the loads in flight are not waited for early
   struct Buf {
     T x[NLX];
-    T c[5][NLC];  // b, diag, y faces, z faces, x faces
+    T c[2][NLC];          // b, diag
+    face_t<T> f[3][NLC];  // x, y, z faces
   };
   auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, l.per[0]);
@@ -902,12 +908,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
     for (int j = 0; j < NLC; ++j) {
       const bool ok = gx >= 0 && coff[j] >= 0;
       const int P = ok ? gx * plane + coff[j] : 0;
-      B.c[4][j] = ok ? l.cf[0][P] : T(0);
+      B.f[0][j] = ok ? l.cf[0][P] : face_t<T>(0);
       if (all) {
         B.c[0][j] = ok ? l.b[P] : T(0);
         B.c[1][j] = ok ? l.diag[P] : T(1);
-        B.c[2][j] = ok ? l.cf[1][P] : T(0);
-        B.c[3][j] = ok ? l.cf[2][P] : T(0);
+        B.f[1][j] = ok ? l.cf[1][P] : face_t<T>(0);
+        B.f[2][j] = ok ? l.cf[2][P] : face_t<T>(0);
       }
     }
   };
@@ -918,10 +924,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = B.c[4][j];
+      c0s[s3 + li] = face_value(B.f[0][j]);
       if (all) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) cs[a][s2 + li] = B.c[a][j];
+        cs[0][s2 + li] = B.c[0][j];
+        cs[1][s2 + li] = B.c[1][j];
+        cs[2][s2 + li] = face_value(B.f[1][j]);
+        cs[3][s2 + li] = face_value(B.f[2][j]);
       }
     }
   };
@@ -1224,9 +1232,10 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     srow[b] = (l.per[1] ? vy : fold(vy, l.ny, 0)) - y0;
     scol[b] = (l.per[2] ? vz : fold(vz, l.nz, 0)) - z0;
   }
-  struct Buf {
+  struct Buf {  // as in k_rbgs_march
     T x[NLX];
-    T c[5][NLC];
+    T c[2][NLC];
+    face_t<T> f[3][NLC];
   };
   auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, px);
@@ -1248,12 +1257,12 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     for (int j = 0; j < NLC; ++j) {
       const bool ok = gx >= 0 && coff[j] >= 0;
       const int P = ok ? gx * plane + coff[j] : 0;
-      B.c[4][j] = ok ? l.cf[0][P] : T(0);
+      B.f[0][j] = ok ? l.cf[0][P] : face_t<T>(0);
       if (all) {
         B.c[0][j] = ok ? l.b[P] : T(0);
         B.c[1][j] = ok ? l.diag[P] : T(0);
-        B.c[2][j] = ok ? l.cf[1][P] : T(0);
-        B.c[3][j] = ok ? l.cf[2][P] : T(0);
+        B.f[1][j] = ok ? l.cf[1][P] : face_t<T>(0);
+        B.f[2][j] = ok ? l.cf[2][P] : face_t<T>(0);
       }
     }
   };
@@ -1264,10 +1273,12 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = B.c[4][j];
+      c0s[s3 + li] = face_value(B.f[0][j]);
       if (all) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) cs[a][s2 + li] = B.c[a][j];
+        cs[0][s2 + li] = B.c[0][j];
+        cs[1][s2 + li] = B.c[1][j];
+        cs[2][s2 + li] = face_value(B.f[1][j]);
+        cs[3][s2 + li] = face_value(B.f[2][j]);
       }
     }
   };
@@ -2103,11 +2114,8 @@ void launch_adj_limiter(hipStream_t s, const StepK& k, const AdjArgs& a) {
                                   double*, double*, double, int, const XFold&, double*);
 RH_INST(float)
 RH_INST(double)
-template void launch_coarsen_faces<double, double>(hipStream_t, int, int, int,
-                                                   const double* const[3], const LevelK<double>&);
-template void launch_coarsen_faces<double, float>(hipStream_t, int, int, int,
-                                                  const double* const[3], const LevelK<float>&);
-template void launch_coarsen_faces<float, float>(hipStream_t, int, int, int,
-                                                 const float* const[3], const LevelK<float>&);
+template void launch_coarsen_faces<double>(hipStream_t, const LevelK<double>&,
+                                           const LevelK<double>&);
+template void launch_coarsen_faces<float>(hipStream_t, const LevelK<float>&, const LevelK<float>&);
 
 }  // namespace rh
