@@ -27,26 +27,28 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fine cell of one launch of each kernel class
 # (every input field read once, every output written once; halo re-reads
 # and cache effects count zero).  T = 4 (mixed) or 8 (FP64) bytes per
-# multigrid value; F = the bytes of a multigrid face coefficient (bfloat16
-# on FP32 levels, double on FP64 levels).
-def face_bytes(T):
-    return 2 if T == 4 else T
+# multigrid value.  A level's operator per cell: FP32 levels one 8-byte
+# record (three faces and the shift in bfloat16), FP64 levels the diagonal
+# and three face arrays (4 T).
+def operator_bytes(T):
+    return 8 if T == 4 else 4 * T
 
 
 def algorithmic_bytes_per_cell(kind, T, iso=False):
-    F = face_bytes(T)
+    O = operator_bytes(T)
     return {
-        # one full red-black sweep in one launch: x, b, diag and the three
-        # + face arrays read, the new x written
-        "rbgs_fine": 4 * T + 3 * F,
-        # one colour of a sweep: other-colour x, own b and diag, all three
-        # + face arrays (own + faces and the neighbours' - faces), own x written
-        "rbgs_fine_colour": 0.5 * T + 1.0 * T + 3 * F + 0.5 * T,
+        # one full red-black sweep in one launch: x, b and the operator
+        # read, the new x written
+        "rbgs_fine": 3 * T + O,
+        # one colour of a sweep: other-colour x, own b, the operator (FP32:
+        # every record, for the own shift and + faces and the neighbours' -
+        # faces; FP64: own diagonal, all three face arrays), own x written
+        "rbgs_fine_colour": 1.5 * T + (O if T == 4 else 0.5 * T + 3 * T),
         # the V-cycle's last sweep, which also reads r and q for z.r, z.q
-        "rbgs_fine_dots": 4 * T + 3 * F + 2 * 8,
-        # residual fused with the restriction (x, b, diag, 3 faces in; coarse
+        "rbgs_fine_dots": 3 * T + O + 2 * 8,
+        # residual fused with the restriction (x, b, operator in; coarse
         # right-hand side out), as the benchmark sizes run it
-        "mg_residual_fine": 3 * T + 3 * F + T / 8,
+        "mg_residual_fine": 2 * T + O + T / 8,
         "restrict_fine": T + T / 8,
         "prolong_fine": T / 8 + 2 * T,
         # zT, p, x, diag, 3 cf in; p, q, x out (x += alpha p of the previous
@@ -54,9 +56,11 @@ def algorithmic_bytes_per_cell(kind, T, iso=False):
         "pcg_direction": T + 6 * 8 + 3 * 8,
         "pcg_update": 3 * 8 + T,            # r, q in; r, b out
         "pcg_precond": T + 2 * 8,           # zT, r, q in (dot products only)
-        "residual_schur": 8 * 8 + 2 * 8 + (T if T == 4 else 0),
+        # ... and, mixed, the FP32 finest level's shift (bfloat16)
+        "residual_schur": 8 * 8 + 2 * 8 + (2 if T == 4 else 0),
         "local_solve": (12 if not iso else 8) * 8 + (7 if not iso else 4) * 8,
-        "step_setup": 3 * 8 + 3 * 8 + (3 * F if T == 4 else 0) + 8,
+        # ... and, mixed, the FP32 finest level's three faces (bfloat16)
+        "step_setup": 3 * 8 + 3 * 8 + (3 * 2 if T == 4 else 0) + 8,
     }.get(kind)
 
 
@@ -79,13 +83,15 @@ def step_bytes_per_cell(st, T, iso=False):
     U^n copied in and the result copied out (3 fields each way), the face
     limiter, one local solve + residual per evaluation (the start, one trial
     per Newton iteration and one per line-search cut), the coarse-level
-    operators per Newton iteration (diagonal of N/7 cells: shift in, diag
-    out) and every linear iteration."""
+    operators per Newton iteration (on N/7 cells: fine shifts or diagonals
+    in, coarse ones out; a bfloat16 shift on FP32 levels) and every linear
+    iteration."""
     b = algorithmic_bytes_per_cell
     evals = 1 + st["newton_its"] + st["ls_cuts"]
     copies = 2 * 3 * 2 * 8
+    S = 2 if T == 4 else T
     return (copies + b("step_setup", T) + evals * (b("local_solve", T, iso) + b("residual_schur", T))
-            + st["newton_its"] * (3 * T / 7.0) + st["lin_its_total"] * linear_iteration_bytes(T))
+            + st["newton_its"] * (3 * S / 7.0) + st["lin_its_total"] * linear_iteration_bytes(T))
 
 
 def host_description():

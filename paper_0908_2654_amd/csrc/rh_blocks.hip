@@ -108,14 +108,15 @@ k_block_inverse(LevelK<T> l, BlockSet<T> bs) {
   const int exy = bs.ey * bs.ez;
   for (int p = threadIdx.x; p < m; p += kBlockThreads) {
     const int lx = p / exy, ly = (p / bs.ez) % bs.ey, lz = p % bs.ez;
-    const long long P = cell_index(s0 + lx, s1 + ly, s2 + lz, l.ny, l.nz);
-    coef[p][0] = (double)l.diag[P];
-    coef[p][1] = lx + 1 < bs.ex ? -(double)face_at(l.cf[0], P) : 0.0;
-    coef[p][2] = lx > 0 ? -(double)face_at(l.cf[0], P - (long long)l.ny * l.nz) : 0.0;
-    coef[p][3] = ly + 1 < bs.ey ? -(double)face_at(l.cf[1], P) : 0.0;
-    coef[p][4] = ly > 0 ? -(double)face_at(l.cf[1], P - l.nz) : 0.0;
-    coef[p][5] = lz + 1 < bs.ez ? -(double)face_at(l.cf[2], P) : 0.0;
-    coef[p][6] = lz > 0 ? -(double)face_at(l.cf[2], P - 1) : 0.0;
+    const int cc[3] = {s0 + lx, s1 + ly, s2 + lz};
+    const long long P = cell_index(cc[0], cc[1], cc[2], l.ny, l.nz);
+    coef[p][0] = (double)diag_of(l, cc, P);
+    coef[p][1] = lx + 1 < bs.ex ? -(double)face_of(l, 0, P) : 0.0;
+    coef[p][2] = lx > 0 ? -(double)face_of(l, 0, P - (long long)l.ny * l.nz) : 0.0;
+    coef[p][3] = ly + 1 < bs.ey ? -(double)face_of(l, 1, P) : 0.0;
+    coef[p][4] = ly > 0 ? -(double)face_of(l, 1, P - l.nz) : 0.0;
+    coef[p][5] = lz + 1 < bs.ez ? -(double)face_of(l, 2, P) : 0.0;
+    coef[p][6] = lz > 0 ? -(double)face_of(l, 2, P - 1) : 0.0;
   }
   __syncthreads();
   const int r = threadIdx.x / kInvTile, c = threadIdx.x % kInvTile;
@@ -223,13 +224,13 @@ __global__ void __launch_bounds__(128) k_block_relax(LevelK<T> l, BlockSet<T> bs
     for (int d = 0; d < 3; ++d) {
       int q[3];
       if (neighbour(c, n, l.per, d, +1, q))
-        off += face_at(l.cf[d], P) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+        off += face_of(l, d, P) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
       if (neighbour(c, n, l.per, d, -1, q)) {
         const long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
-        off += face_at(l.cf[d], Q) * l.x[Q];
+        off += face_of(l, d, Q) * l.x[Q];
       }
     }
-    r[p] = l.b[P] - (l.diag[P] * l.x[P] - off);
+    r[p] = l.b[P] - (diag_of(l, c, P) * l.x[P] - off);
   }
   __syncthreads();
   if (p < m) {

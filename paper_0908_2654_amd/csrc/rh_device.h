@@ -76,6 +76,37 @@ __device__ inline bool neighbour(const int (&c)[3], const int (&n)[3], const int
   return true;
 }
 
+// Level operators: the + face coefficient of cell i along axis d, and the
+// diagonal of cell c (index i); FP32 levels form it from the packed record
+// with op_diag, the same sum the marching kernels form from staged values.
+__device__ inline double face_of(const LevelK<double>& l, int d, long long i) {
+  return l.cf[d][i];
+}
+__device__ inline float face_of(const LevelK<float>& l, int d, long long i) {
+  return bf16_value(l.op[i].f[d]);
+}
+__device__ inline double diag_of(const LevelK<double>& l, const int (&)[3], long long i) {
+  return l.diag[i];
+}
+__device__ inline float diag_of(const LevelK<float>& l, const int (&c)[3], long long i) {
+  const int n[3] = {l.nx, l.ny, l.nz};
+  float f[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int q[3];
+    f[2 * d] = neighbour(c, n, l.per, d, +1, q) ? face_of(l, d, i) : 0.0f;
+    f[2 * d + 1] = neighbour(c, n, l.per, d, -1, q)
+                       ? face_of(l, d, ((long long)q[0] * l.ny + q[1]) * l.nz + q[2])
+                       : 0.0f;
+  }
+  return op_diag(bf16_value(l.op[i].s), f[0], f[1], f[2], f[3], f[4], f[5]);
+}
+__device__ inline void put_face(const LevelK<double>& l, int d, long long i, double v) {
+  l.cf[d][i] = v;
+}
+__device__ inline void put_face(const LevelK<float>& l, int d, long long i, double v) {
+  l.op[i].f[d] = bf16_round((float)v);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Give each XCD a contiguous range of tile indices, so tiles that share

@@ -309,7 +309,7 @@ rh_status groups_eval(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const GSt
     r.Kgg = h->K + (long long)(g * h->G + g) * N;
     r.rS = s->rS;
     r.diag64 = s->diag64;
-    r.diag32 = mixed ? s->L32[0].diag : nullptr;
+    r.op32 = mixed ? s->L32[0].op : nullptr;
     r.fE_out = fE ? fE + g * N : nullptr;
     launch_residual(h->stream, kg[g], r, s->part);
     GHIPCHK(hipGetLastError());

@@ -290,8 +290,7 @@ size_t layout(rh_handle* h, const rh_params& p, const Plan& pl, char* base) {
       L.x2 = cv.take<float>(n);
       L.b = cv.take<float>(n);
       L.r = cv.take<float>(n);
-      L.diag = cv.take<float>(n);
-      for (int a = 0; a < 3; ++a) L.cf[a] = cv.take<face_t<float>>(n);
+      L.op = cv.take<Op16>(n);
     } else {
       LevelK<double>& L = h->L64[l];
       L.nx = d[0]; L.ny = d[1]; L.nz = d[2]; L.N = n;
@@ -517,13 +516,11 @@ rh_status setup_step(rh_handle* h, StepK& k, const double* src, const double* En
                      const double* y2n = nullptr) {
   const bool mixed = h->p.precision == RH_PREC_MIXED;
   phase_mark(h, PH_SETUP);
-  face_t<float>* c32[3] = {nullptr, nullptr, nullptr};
-  if (mixed)
-    for (int a = 0; a < 3; ++a) c32[a] = h->L32[0].cf[a];
+  Op16* op32 = mixed ? h->L32[0].op : nullptr;
   {
     Timed tm0(h, KK_SETUP);
     launch_step_setup(h->stream, k, En ? En : h->En, nn ? nn : h->nn, y1n, y2n, src, h->cf64[0],
-                      h->cf64[1], h->cf64[2], c32[0], c32[1], c32[2], h->rhsn, h->part);
+                      h->cf64[1], h->cf64[2], op32, h->rhsn, h->part);
   }
   HIPCHK(hipGetLastError());
   rh_status st = sync_reductions(h, kAllSlots);
@@ -709,7 +706,7 @@ rh_status eval_state(rh_handle* h, const StepK& k, const StateBuf& cur, const do
   r.rhsn = h->rhsn;
   r.BCn = out.loc[0]; r.Bfn = out.loc[2];
   r.rS = h->rS; r.diag64 = h->diag64;
-  r.diag32 = h->p.precision == RH_PREC_MIXED ? h->L32[0].diag : nullptr;
+  r.op32 = h->p.precision == RH_PREC_MIXED ? h->L32[0].op : nullptr;
   r.fE_out = fE_out;
   {
     Timed tm(h, KK_RESID);

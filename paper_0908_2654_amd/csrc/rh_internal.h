@@ -52,23 +52,8 @@ struct StepK {
   double src_frac;
 };
 
-// Face coefficients of a multigrid level: FP64 levels hold them in double,
-// FP32 levels in bfloat16 (the upper 16 bits of an FP32 pattern, rounded to
-// nearest even).  An FP32 level's diagonal is formed from its rounded faces
-// plus the exact shift, so the stored operator stays a symmetric M-matrix
-// whose energy differs from the exact one's by at most a factor 1 +- 2^-8
-// (every face and the shift enter the energy with non-negative weight).
-template <class T>
-struct FaceOf {
-  using type = T;
-};
-template <>
-struct FaceOf<float> {
-  using type = uint16_t;
-};
-template <class T>
-using face_t = typename FaceOf<T>::type;
-
+// bfloat16 <-> float: a bfloat16 is the upper half of an FP32 bit pattern
+// (rounded to nearest even; the values stored here are finite).
 __host__ __device__ inline float bf16_value(uint16_t h) {
   const uint32_t u = (uint32_t)h << 16;
   float f;
@@ -81,29 +66,41 @@ __host__ __device__ inline uint16_t bf16_round(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-// A face value as a level of type T reads it / stores it.
+
+// Operator of an FP32 multigrid level, one 8-byte record per cell (a
+// single load): the cell's + face coefficients along x, y, z and its shift
+// (the diagonal minus the six face coefficients of the cell), in bfloat16.
+// The diagonal is formed where it is used, as op_diag below, so the level's
+// operator is a symmetric M-matrix whose energy is within 1 +- 2^-8 of the
+// exact operator's (faces and shift are non-negative and each enters the
+// energy with a non-negative weight).  FP64 levels keep the diagonal and the
+// faces as separate double arrays.
+struct __align__(8) Op16 {
+  uint16_t f[3];  // + faces along x, y, z (0 on a non-periodic last face)
+  uint16_t s;     // shift
+};
+// The diagonal of an FP32 level from a cell's shift and its six faces, in
+// this order everywhere (absent faces enter as 0).
+__host__ __device__ inline float op_diag(float s, float xp, float xm, float yp, float ym, float zp,
+                                         float zm) {
+  return (((((s + xp) + xm) + yp) + ym) + zp) + zm;
+}
+
 template <class T>
-__host__ __device__ inline T face_at(const T* c, long long i) {
-  return c[i];
-}
-__host__ __device__ inline float face_at(const uint16_t* c, long long i) {
-  return bf16_value(c[i]);
-}
-__host__ __device__ inline void face_put(double* c, long long i, double v) { c[i] = v; }
-__host__ __device__ inline void face_put(uint16_t* c, long long i, double v) {
-  c[i] = bf16_round((float)v);
-}
-// A face in its stored form -> its value.
-__host__ __device__ inline float face_value(uint16_t h) { return bf16_value(h); }
-__host__ __device__ inline double face_value(double v) { return v; }
-// The value an FP32 level holds for the face v.
-__host__ __device__ inline double face_rounded(double v) {
-  return (double)bf16_value(bf16_round((float)v));
-}
+struct LevelOp;
+template <>
+struct LevelOp<double> {
+  double* diag;   // diagonal of the Schur operator
+  double* cf[3];  // + face coefficients (dimensionless, 0 on a non-periodic last face)
+};
+template <>
+struct LevelOp<float> {
+  Op16* op;       // packed operator records
+};
 
 // One multigrid level (T = float or double).
 template <class T>
-struct LevelK {
+struct LevelK : LevelOp<T> {
   int nx, ny, nz;
   long long N;
   int per[3];           // periodic per dimension
@@ -111,8 +108,6 @@ struct LevelK {
   T* x2;                // second correction buffer (output of a fused sweep)
   T* b;                 // right-hand side
   T* r;                 // residual scratch
-  T* diag;              // diagonal of the Schur operator
-  face_t<T>* cf[3];     // + face coefficients (dimensionless, 0 on a non-periodic last face)
 };
 
 // Source-centred boxes of one multigrid level for the block smoother
@@ -183,7 +178,7 @@ void launch_scale_field(hipStream_t s, long long N, double scale, const double* 
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* y1n, const double* y2n,
                        const double* src, double* cf64_x, double* cf64_y, double* cf64_z,
-                       uint16_t* cf32_x, uint16_t* cf32_y, uint16_t* cf32_z, double* rhsn,
+                       Op16* op32, double* rhsn,
                        double* part);
 
 // mode 0: solve the local equations at E = E_k + lam dE (dE may be null);
@@ -205,7 +200,8 @@ struct ResidArgs {
   const double* E; const double* n; const double* En; const double* nn;
   const double* cf[3]; const double* rhsn;
   const double* BCn; const double* Bfn;
-  double* rS; double* diag64; float* diag32; double* fE_out;
+  double* rS; double* diag64; double* fE_out;
+  Op16* op32;  // FP32 finest level: its shift is written (faces come from the step setup)
   // multigroup (all null for the grey step): helium densities of the state
   // and of U^n, and the group's Schur terms from the local elimination
   // (kB = sum_s J_gs (B^-1 f)_s, Kgg = sum_s J_gs (B^-1 C)_sg), which then

@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(kBlock)
 k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ nn,
              const double* __restrict__ y1n, const double* __restrict__ y2n,
              const double* __restrict__ src, double* __restrict__ cfx, double* __restrict__ cfy,
-             double* __restrict__ cfz, uint16_t* __restrict__ c32x, uint16_t* __restrict__ c32y,
-             uint16_t* __restrict__ c32z, double* __restrict__ rhsn, double* __restrict__ part) {
+             double* __restrict__ cfz, Op16* __restrict__ op32, double* __restrict__ rhsn,
+             double* __restrict__ part) {
   const int per[3] = {k.bc[0] == RH_BC_PERIODIC, k.bc[2] == RH_BC_PERIODIC,
                       k.bc[4] == RH_BC_PERIODIC};
   const int n[3] = {k.nx, k.ny, k.nz};
@@ -65,7 +65,6 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
   };
   double emax = 0.0, smax = 0.0, bad = 0.0;
   double* cfo[3] = {cfx, cfy, cfz};
-  uint16_t* c32[3] = {c32x, c32y, c32z};  // faces of the FP32 finest level (may be null)
   // blocks of one XCD take consecutive cells, so the y neighbours a block
   // reads were loaded by its neighbours on the same XCD (shared L2)
   for (long long idx = xcd_tile(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x;
@@ -90,7 +89,7 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
         Ln += cfp * (EQ - EP);
       }
       cfo[d][idx] = cfp;
-      if (c32[d]) face_put(c32[d], idx, cfp);
+      if (op32) op32[idx].f[d] = bf16_round((float)cfp);  // FP32 finest level
       if (k.theta_lt1 && neighbour(c, n, per, d, -1, q)) {
         long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         double EQ = En[Q];
@@ -115,10 +114,9 @@ k_step_setup(StepK k, const double* __restrict__ En, const double* __restrict__ 
 
 void launch_step_setup(hipStream_t s, const StepK& k, const double* En, const double* nn,
                        const double* y1n, const double* y2n, const double* src, double* cfx,
-                       double* cfy, double* cfz, uint16_t* c32x, uint16_t* c32y,
-                       uint16_t* c32z, double* rhsn, double* part) {
+                       double* cfy, double* cfz, Op16* op32, double* rhsn, double* part) {
   hipLaunchKernelGGL(k_step_setup, dim3(red_grid(k.N)), dim3(kBlock), 0, s, k, En, nn, y1n, y2n,
-                     src, cfx, cfy, cfz, c32x, c32y, c32z, rhsn, part);
+                     src, cfx, cfy, cfz, op32, rhsn, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,7 +410,6 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
     const double EP = a.E[idx];
     const double nP = a.n[idx];
     double LE = 0.0, csum = 0.0;
-    double csum32 = 0.0;  // the same faces as the FP32 finest level holds them
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int q[3];
@@ -420,14 +417,12 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
         const double cf = a.cf[d][idx];
         LE += cf * (a.E[cell_index(q[0], q[1], q[2], k.ny, k.nz)] - EP);
         csum += cf;
-        if (a.diag32) csum32 += face_rounded(cf);
       }
       if (neighbour(c, nd, per, d, -1, q)) {
         const long long Q = cell_index(q[0], q[1], q[2], k.ny, k.nz);
         const double cf = a.cf[d][Q];
         LE += cf * (a.E[Q] - EP);
         csum += cf;
-        if (a.diag32) csum32 += face_rounded(cf);
       }
     }
     bool bnd = (c[0] == 0 || c[0] == k.nx - 1 || c[1] == 0 || c[1] == k.ny - 1 || c[2] == 0 ||
@@ -453,8 +448,8 @@ k_residual(StepK k, ResidArgs a, double* __restrict__ part) {
     }
     if (a.rS) a.rS[idx] = rS;
     if (a.diag64) a.diag64[idx] = diag;
-    // FP32 level: its rounded faces plus the exact shift (diag - csum)
-    if (a.diag32) a.diag32[idx] = (float)((diag - csum) + csum32);
+    // FP32 finest level: the shift, diagonal minus the faces
+    if (a.op32) a.op32[idx].s = bf16_round((float)(diag - csum));
     if (a.fE_out) a.fE_out[idx] = fE;
     sfe += (fE / k.E_s) * (fE / k.E_s);
     rmax = fmax(rmax, fabs(rS));
@@ -590,9 +585,8 @@ void launch_finalize(hipStream_t s, const double* part, double* out, unsigned ma
 // multigrid: coarse operators
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(kBlock)
-k_coarsen_faces(int fny, int fnz, const face_t<T>* __restrict__ fx,
-                const face_t<T>* __restrict__ fy, const face_t<T>* __restrict__ fz, LevelK<T> c) {
+__global__ void __launch_bounds__(kBlock) k_coarsen_faces(LevelK<T> f, LevelK<T> c) {
+  const int fny = f.ny, fnz = f.nz;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
        idx += (long long)blockDim.x * gridDim.x) {
     int I, J, K;
@@ -601,21 +595,20 @@ k_coarsen_faces(int fny, int fnz, const face_t<T>* __restrict__ fx,
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
-        sx += (double)face_at(fx, cell_index(2 * I + 1, 2 * J + a, 2 * K + b, fny, fnz));
-        sy += (double)face_at(fy, cell_index(2 * I + a, 2 * J + 1, 2 * K + b, fny, fnz));
-        sz += (double)face_at(fz, cell_index(2 * I + a, 2 * J + b, 2 * K + 1, fny, fnz));
+        sx += (double)face_of(f, 0, cell_index(2 * I + 1, 2 * J + a, 2 * K + b, fny, fnz));
+        sy += (double)face_of(f, 1, cell_index(2 * I + a, 2 * J + 1, 2 * K + b, fny, fnz));
+        sz += (double)face_of(f, 2, cell_index(2 * I + a, 2 * J + b, 2 * K + 1, fny, fnz));
       }
     // mean of the 4 fine faces, times 1/4 for the doubled cell width
-    face_put(c.cf[0], idx, 0.0625 * sx);
-    face_put(c.cf[1], idx, 0.0625 * sy);
-    face_put(c.cf[2], idx, 0.0625 * sz);
+    put_face(c, 0, idx, 0.0625 * sx);
+    put_face(c, 1, idx, 0.0625 * sy);
+    put_face(c, 2, idx, 0.0625 * sz);
   }
 }
 
 template <class T>
 void launch_coarsen_faces(hipStream_t s, const LevelK<T>& f, const LevelK<T>& c) {
-  hipLaunchKernelGGL((k_coarsen_faces<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f.ny, f.nz,
-                     f.cf[0], f.cf[1], f.cf[2], c);
+  hipLaunchKernelGGL((k_coarsen_faces<T>), dim3(red_grid(c.N)), dim3(kBlock), 0, s, f, c);
 }
 
 // Sum of a cell's interior face coefficients (6 faces).
@@ -626,15 +619,19 @@ __device__ inline double face_sum(const LevelK<T>& l, const int (&c)[3], long lo
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     int q[3];
-    if (neighbour(c, n, l.per, d, +1, q)) s += (double)face_at(l.cf[d], idx);
+    if (neighbour(c, n, l.per, d, +1, q)) s += (double)face_of(l, d, idx);
     if (neighbour(c, n, l.per, d, -1, q))
-      s += (double)face_at(l.cf[d], cell_index(q[0], q[1], q[2], l.ny, l.nz));
+      s += (double)face_of(l, d, cell_index(q[0], q[1], q[2], l.ny, l.nz));
   }
   return s;
 }
 
+// Coarse shift = mean of the eight children's shifts (shift = diagonal
+// minus the cell's faces); FP64 levels store the diagonal (coarse shift plus
+// the coarse faces), FP32 levels the shift itself.
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_coarse_diag(LevelK<T> f, LevelK<T> c) {
+  constexpr bool kF32 = std::is_same<T, float>::value;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.N;
        idx += (long long)blockDim.x * gridDim.x) {
     int C[3];
@@ -645,9 +642,15 @@ __global__ void __launch_bounds__(kBlock) k_coarse_diag(LevelK<T> f, LevelK<T> c
         for (int d = 0; d < 2; ++d) {
           int F[3] = {2 * C[0] + a, 2 * C[1] + b, 2 * C[2] + d};
           long long fi = cell_index(F[0], F[1], F[2], f.ny, f.nz);
-          sh += (double)f.diag[fi] - face_sum(f, F, fi);
+          if constexpr (kF32)
+            sh += (double)bf16_value(f.op[fi].s);
+          else
+            sh += (double)f.diag[fi] - face_sum(f, F, fi);
         }
-    c.diag[idx] = (T)(0.125 * sh + face_sum(c, C, idx));
+    if constexpr (kF32)
+      c.op[idx].s = bf16_round((float)(0.125 * sh));
+    else
+      c.diag[idx] = (T)(0.125 * sh + face_sum(c, C, idx));
   }
 }
 
@@ -673,16 +676,16 @@ __global__ void __launch_bounds__(1024) k_coarsest_inverse(LevelK<T> c, double* 
     for (int P = 0; P < n; ++P) {
       int C[3];
       cell_ijk(P, c.ny, c.nz, C[0], C[1], C[2]);
-      A[(long long)P * n + P] += (double)c.diag[P];
+      A[(long long)P * n + P] += (double)diag_of(c, C, P);
       for (int d = 0; d < 3; ++d) {
         int q[3];
         if (neighbour(C, nd, c.per, d, +1, q)) {
           int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
-          A[(long long)P * n + Q] -= (double)face_at(c.cf[d], P);
+          A[(long long)P * n + Q] -= (double)face_of(c, d, P);
         }
         if (neighbour(C, nd, c.per, d, -1, q)) {
           int Q = (int)cell_index(q[0], q[1], q[2], c.ny, c.nz);
-          A[(long long)P * n + Q] -= (double)face_at(c.cf[d], Q);
+          A[(long long)P * n + Q] -= (double)face_of(c, d, Q);
         }
       }
     }
@@ -746,10 +749,10 @@ __device__ inline T offdiag_sum(const LevelK<T>& l, const int (&c)[3], long long
   for (int d = 0; d < 3; ++d) {
     int q[3];
     if (neighbour(c, n, l.per, d, +1, q))
-      s += face_at(l.cf[d], idx) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
+      s += face_of(l, d, idx) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
     if (neighbour(c, n, l.per, d, -1, q)) {
       long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
-      s += face_at(l.cf[d], Q) * l.x[Q];
+      s += face_of(l, d, Q) * l.x[Q];
     }
   }
   return s;
@@ -766,7 +769,7 @@ __global__ void __launch_bounds__(kBlock) k_rbgs(LevelK<T> l, int color, int zer
     if (((c[0] + c[1] + c[2]) & 1) != color) continue;
     T s = l.b[idx];
     if (!zero_init) s += offdiag_sum(l, c, idx);
-    l.x[idx] = s / l.diag[idx];
+    l.x[idx] = s / diag_of(l, c, idx);
   }
 }
 
@@ -817,6 +820,55 @@ template <>
 struct MarchTile<double> {
   static constexpr int TY = 8, TZ = 32, NT = 256;
 };
+// Prefetch registers of one staged coefficient slot of a marching kernel:
+// FP64 levels hold the diagonal and the three + faces, FP32 levels the raw
+// packed record, decoded only when it is staged to LDS (so the loads in
+// flight are not waited for early).  In LDS the "diagonal" plane holds the
+// diagonal (FP64) or the shift (FP32; the diagonal is then op_diag of the
+// staged shift and faces).
+template <class T>
+struct CoefRegs {
+  T d, f0, f1, f2;
+};
+template <>
+struct CoefRegs<float> {
+  uint2 raw;  // Op16 as two dwords: x = f0 | f1 << 16, y = f2 | s << 16
+};
+__device__ inline void load_coef(const LevelK<double>& l, long long P, bool ok, bool all,
+                                 double d_out, CoefRegs<double>& r) {
+  r.f0 = ok ? l.cf[0][P] : 0.0;
+  if (all) {
+    r.d = ok ? l.diag[P] : d_out;
+    r.f1 = ok ? l.cf[1][P] : 0.0;
+    r.f2 = ok ? l.cf[2][P] : 0.0;
+  }
+}
+__device__ inline void load_coef(const LevelK<float>& l, long long P, bool ok, bool, double,
+                                 CoefRegs<float>& r) {
+  r.raw = ok ? reinterpret_cast<const uint2*>(l.op)[P] : make_uint2(0u, 0u);
+}
+__device__ inline double coef_f0(const CoefRegs<double>& r) { return r.f0; }
+__device__ inline double coef_f1(const CoefRegs<double>& r) { return r.f1; }
+__device__ inline double coef_f2(const CoefRegs<double>& r) { return r.f2; }
+__device__ inline double coef_d(const CoefRegs<double>& r) { return r.d; }
+__device__ inline float coef_f0(const CoefRegs<float>& r) { return __uint_as_float(r.raw.x << 16); }
+__device__ inline float coef_f1(const CoefRegs<float>& r) {
+  return __uint_as_float(r.raw.x & 0xFFFF0000u);
+}
+__device__ inline float coef_f2(const CoefRegs<float>& r) { return __uint_as_float(r.raw.y << 16); }
+__device__ inline float coef_d(const CoefRegs<float>& r) {
+  return __uint_as_float(r.raw.y & 0xFFFF0000u);
+}
+// Diagonal of a staged cell from the staged "diagonal" value and the six
+// staged faces (+x, -x, +y, -y, +z, -z).
+__device__ inline double staged_diag(double d, double, double, double, double, double, double) {
+  return d;
+}
+__device__ inline float staged_diag(float s, float xp, float xm, float yp, float ym, float zp,
+                                    float zm) {
+  return op_diag(s, xp, xm, yp, ym, zp, zm);
+}
+
 template <class T>
 struct ResidTile;
 template <>
@@ -881,12 +933,10 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
     const int t = tid + j * NT;
     coff[j] = t < CN ? inplane(t / CZ, t % CZ) : -1;
   }
-  // faces stay in their stored form (bfloat16 bits on FP32 levels) until
-  // they are staged, so the loads in flight are not waited for early
   struct Buf {
     T x[NLX];
-    T c[2][NLC];          // b, diag
-    face_t<T> f[3][NLC];  // x, y, z faces
+    T b[NLC];
+    CoefRegs<T> k[NLC];
   };
   auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, l.per[0]);
@@ -908,13 +958,8 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
     for (int j = 0; j < NLC; ++j) {
       const bool ok = gx >= 0 && coff[j] >= 0;
       const int P = ok ? gx * plane + coff[j] : 0;
-      B.f[0][j] = ok ? l.cf[0][P] : face_t<T>(0);
-      if (all) {
-        B.c[0][j] = ok ? l.b[P] : T(0);
-        B.c[1][j] = ok ? l.diag[P] : T(1);
-        B.f[1][j] = ok ? l.cf[1][P] : face_t<T>(0);
-        B.f[2][j] = ok ? l.cf[2][P] : face_t<T>(0);
-      }
+      load_coef(l, P, ok, all, 1.0, B.k[j]);
+      if (all) B.b[j] = ok ? l.b[P] : T(0);
     }
   };
   auto stash_c = [&](int p, bool all, const Buf& B) {
@@ -924,12 +969,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = face_value(B.f[0][j]);
+      c0s[s3 + li] = coef_f0(B.k[j]);
       if (all) {
-        cs[0][s2 + li] = B.c[0][j];
-        cs[1][s2 + li] = B.c[1][j];
-        cs[2][s2 + li] = face_value(B.f[1][j]);
-        cs[3][s2 + li] = face_value(B.f[2][j]);
+        cs[0][s2 + li] = B.b[j];
+        cs[1][s2 + li] = coef_d(B.k[j]);
+        cs[2][s2 + li] = coef_f1(B.k[j]);
+        cs[3][s2 + li] = coef_f2(B.k[j]);
       }
     }
   };
@@ -969,7 +1014,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       off += c1[q - HZ] * cur[q - HZ];
       off += c2[q] * cur[q + 1];
       off += c2[q - 1] * cur[q - 1];
-      nv[j] = (cb[q] + off) / cd[q];
+      nv[j] = (cb[q] + off) / staged_diag(cd[q], c0c[q], c0m[q], c1[q], c1[q - HZ], c2[q], c2[q - 1]);
     }
 #pragma unroll
     for (int j = 0; j < NP; ++j)
@@ -1102,7 +1147,7 @@ __global__ void __launch_bounds__(kBlock) k_mg_residual(LevelK<T> l) {
        idx += (long long)blockDim.x * gridDim.x) {
     int c[3];
     cell_ijk(idx, l.ny, l.nz, c[0], c[1], c[2]);
-    l.r[idx] = l.b[idx] - (l.diag[idx] * l.x[idx] - offdiag_sum(l, c, idx));
+    l.r[idx] = l.b[idx] - (diag_of(l, c, idx) * l.x[idx] - offdiag_sum(l, c, idx));
   }
 }
 
@@ -1234,8 +1279,8 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
   }
   struct Buf {  // as in k_rbgs_march
     T x[NLX];
-    T c[2][NLC];
-    face_t<T> f[3][NLC];
+    T b[NLC];
+    CoefRegs<T> k[NLC];
   };
   auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, px);
@@ -1257,13 +1302,8 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     for (int j = 0; j < NLC; ++j) {
       const bool ok = gx >= 0 && coff[j] >= 0;
       const int P = ok ? gx * plane + coff[j] : 0;
-      B.f[0][j] = ok ? l.cf[0][P] : face_t<T>(0);
-      if (all) {
-        B.c[0][j] = ok ? l.b[P] : T(0);
-        B.c[1][j] = ok ? l.diag[P] : T(0);
-        B.f[1][j] = ok ? l.cf[1][P] : face_t<T>(0);
-        B.f[2][j] = ok ? l.cf[2][P] : face_t<T>(0);
-      }
+      load_coef(l, P, ok, all, 0.0, B.k[j]);
+      if (all) B.b[j] = ok ? l.b[P] : T(0);
     }
   };
   auto stash_c = [&](int p, bool all, const Buf& B) {
@@ -1273,12 +1313,12 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = face_value(B.f[0][j]);
+      c0s[s3 + li] = coef_f0(B.k[j]);
       if (all) {
-        cs[0][s2 + li] = B.c[0][j];
-        cs[1][s2 + li] = B.c[1][j];
-        cs[2][s2 + li] = face_value(B.f[1][j]);
-        cs[3][s2 + li] = face_value(B.f[2][j]);
+        cs[0][s2 + li] = B.b[j];
+        cs[1][s2 + li] = coef_d(B.k[j]);
+        cs[2][s2 + li] = coef_f1(B.k[j]);
+        cs[3][s2 + li] = coef_f2(B.k[j]);
       }
     }
   };
@@ -1341,7 +1381,8 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
         off += c1[q - HZ] * cur[q - HZ];
         off += c2[q] * cur[q + 1];
         off += c2[q - 1] * cur[q - 1];
-        r[q] = cb[q] - (cd[q] * cur[q] - off);
+        const T dq = staged_diag(cd[q], c0c[q], c0m[q], c1[q], c1[q - HZ], c2[q], c2[q - 1]);
+        r[q] = cb[q] - (dq * cur[q] - off);
       }
     }
     if (i + 2 <= i1 + 1) stash_x(i + 2, now);

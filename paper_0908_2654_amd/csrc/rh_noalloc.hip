@@ -146,8 +146,8 @@ extern "C" rh_status rh_residual_noalloc(const rh_params* p, void* hip_stream, d
 
   // face limiter from U^n, constant part of f_E and the norm scale E_s
   StepK k = step_scalars(*p, t_n, dt);
-  launch_step_setup(s, k, E_n, nHI_n, nullptr, nullptr, src, cf[0], cf[1], cf[2], nullptr, nullptr,
-                    nullptr, rhsn, part);
+  launch_step_setup(s, k, E_n, nHI_n, nullptr, nullptr, src, cf[0], cf[1], cf[2], nullptr, rhsn,
+                    part);
   if (hipGetLastError() != hipSuccess) return hip_fail("step setup");
   if ((st = finalize_to_host(s, part, out,
                              slot_bit(RS_EMAX) | slot_bit(RS_SMAX) | slot_bit(RS_NONFINITE),
