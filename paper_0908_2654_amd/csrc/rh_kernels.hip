@@ -1282,43 +1282,49 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
     T b[NLC];
     CoefRegs<T> k[NLC];
   };
+  // Every lane loads (slots outside the grid read cell 0) and those slots
+  // are zeroed when staged, so no loaded value is used before its staging
+  // (0.77 against 1.01 ms with masked loads on the 512^3 finest level; the
+  // sweep measured the other way round and keeps masked loads).
   auto fetch_x = [&](int p, Buf& B) {
     const int gx = wrap(p, l.nx, px);
 #pragma unroll
     for (int j = 0; j < NLX; ++j)
-      B.x[j] = (gx >= 0 && xoff[j] >= 0) ? l.x[gx * plane + xoff[j]] : T(0);
+      B.x[j] = l.x[(gx >= 0 && xoff[j] >= 0) ? gx * plane + xoff[j] : 0];
   };
   auto stash_x = [&](int p, const Buf& B) {
     T* dst = xs + pmod(p, 4) * PL;
+    const bool pok = wrap(p, l.nx, px) >= 0;
 #pragma unroll
     for (int j = 0; j < NLX; ++j) {
       const int t = tid + j * NT;
-      if (t < PL) dst[t] = B.x[j];
+      if (t < PL) dst[t] = (pok && xoff[j] >= 0) ? B.x[j] : T(0);
     }
   };
   auto fetch_c = [&](int p, bool all, Buf& B) {
     const int gx = wrap(p, l.nx, px);
 #pragma unroll
     for (int j = 0; j < NLC; ++j) {
-      const bool ok = gx >= 0 && coff[j] >= 0;
-      const int P = ok ? gx * plane + coff[j] : 0;
-      load_coef(l, P, ok, all, 0.0, B.k[j]);
-      if (all) B.b[j] = ok ? l.b[P] : T(0);
+      const int P = (gx >= 0 && coff[j] >= 0) ? gx * plane + coff[j] : 0;
+      load_coef(l, P, true, all, 0.0, B.k[j]);
+      if (all) B.b[j] = l.b[P];
     }
   };
   auto stash_c = [&](int p, bool all, const Buf& B) {
     const int s2 = pmod(p, 2) * CP, s3 = pmod(p, 3) * CP;
+    const bool pok = wrap(p, l.nx, px) >= 0;
 #pragma unroll
     for (int j = 0; j < NLC; ++j) {
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = coef_f0(B.k[j]);
+      const bool ok = pok && coff[j] >= 0;
+      c0s[s3 + li] = ok ? coef_f0(B.k[j]) : T(0);
       if (all) {
-        cs[0][s2 + li] = B.b[j];
-        cs[1][s2 + li] = coef_d(B.k[j]);
-        cs[2][s2 + li] = coef_f1(B.k[j]);
-        cs[3][s2 + li] = coef_f2(B.k[j]);
+        cs[0][s2 + li] = ok ? B.b[j] : T(0);
+        cs[1][s2 + li] = ok ? coef_d(B.k[j]) : T(0);
+        cs[2][s2 + li] = ok ? coef_f1(B.k[j]) : T(0);
+        cs[3][s2 + li] = ok ? coef_f2(B.k[j]) : T(0);
       }
     }
   };
