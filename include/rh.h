@@ -83,7 +83,10 @@ typedef struct rh_params {
   double alphaB_const;         /* cm^3 s^-1 (paper: 2.59e-13)                            */
   int32_t cosmology;           /* RH_COSMO_*: expansion factor a(t), Hubble rate H(t)    */
   int32_t precision;           /* RH_PREC_FP64: all FP64; _MIXED: FP32 V-cycles inside  */
-                               /* FP64 defect correction                                 */
+                               /* the FP64 outer iteration, each FP32 level's operator   */
+                               /* held as bfloat16 faces and shift (diagonal minus the   */
+                               /* faces), 8 bytes per cell; the outer iteration and the  */
+                               /* Newton residual stay on the exact FP64 operator        */
   double hubble_h, Omega_m, Omega_L;
   double theta;                /* time-centring of the theta method, (0, 1]; 1 = backward Euler */
   double E_floor;              /* floor of face-mean E in the limiter (default 1e-40)    */
