@@ -213,24 +213,14 @@ __global__ void __launch_bounds__(128) k_block_relax(LevelK<T> l, BlockSet<T> bs
   const int m = bs.m;
   const int blk = b0 + blockIdx.x;
   const int s0 = bs.start[3 * blk], s1 = bs.start[3 * blk + 1], s2 = bs.start[3 * blk + 2];
-  const int n[3] = {l.nx, l.ny, l.nz};
   const int p = threadIdx.x;
   long long P = -1;
   if (p < m) {
     const int c[3] = {s0 + p / (bs.ey * bs.ez), s1 + (p / bs.ez) % bs.ey, s2 + p % bs.ez};
     P = cell_index(c[0], c[1], c[2], l.ny, l.nz);
-    T off = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      int q[3];
-      if (neighbour(c, n, l.per, d, +1, q))
-        off += face_of(l, d, P) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
-      if (neighbour(c, n, l.per, d, -1, q)) {
-        const long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
-        off += face_of(l, d, Q) * l.x[Q];
-      }
-    }
-    r[p] = l.b[P] - (diag_of(l, c, P) * l.x[P] - off);
+    T off, dg;
+    row_terms(l, c, P, true, off, dg);
+    r[p] = l.b[P] - (dg * l.x[P] - off);
   }
   __syncthreads();
   if (p < m) {

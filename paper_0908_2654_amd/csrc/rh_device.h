@@ -101,6 +101,53 @@ __device__ inline float diag_of(const LevelK<float>& l, const int (&c)[3], long 
   }
   return op_diag(bf16_value(l.op[i].s), f[0], f[1], f[2], f[3], f[4], f[5]);
 }
+// One row of a level's operator at cell c (index i): the off-diagonal sum
+// sum_faces f x_neighbour in the order +x, -x, +y, -y, +z, -z (when want_off)
+// and the diagonal.  FP32 levels read the cell's record once (one 8-byte
+// load) and each - face once, for both.
+__device__ inline void row_terms(const LevelK<double>& l, const int (&c)[3], long long i,
+                                 bool want_off, double& off, double& diag) {
+  const int n[3] = {l.nx, l.ny, l.nz};
+  double s = 0.0;
+  if (want_off) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int q[3];
+      if (neighbour(c, n, l.per, d, +1, q))
+        s += l.cf[d][i] * l.x[((long long)q[0] * l.ny + q[1]) * l.nz + q[2]];
+      if (neighbour(c, n, l.per, d, -1, q)) {
+        const long long Q = ((long long)q[0] * l.ny + q[1]) * l.nz + q[2];
+        s += l.cf[d][Q] * l.x[Q];
+      }
+    }
+  }
+  off = s;
+  diag = l.diag[i];
+}
+__device__ inline void row_terms(const LevelK<float>& l, const int (&c)[3], long long i,
+                                 bool want_off, float& off, float& diag) {
+  const int n[3] = {l.nx, l.ny, l.nz};
+  const uint2 rec = reinterpret_cast<const uint2*>(l.op)[i];
+  const float fp[3] = {__uint_as_float(rec.x << 16), __uint_as_float(rec.x & 0xFFFF0000u),
+                       __uint_as_float(rec.y << 16)};
+  float fm[3];
+  float s = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int q[3];
+    if (want_off && neighbour(c, n, l.per, d, +1, q))
+      s += fp[d] * l.x[((long long)q[0] * l.ny + q[1]) * l.nz + q[2]];
+    fm[d] = 0.0f;
+    if (neighbour(c, n, l.per, d, -1, q)) {
+      const long long Q = ((long long)q[0] * l.ny + q[1]) * l.nz + q[2];
+      fm[d] = face_of(l, d, Q);
+      if (want_off) s += fm[d] * l.x[Q];
+    }
+  }
+  off = s;
+  // a + face towards a non-periodic wall is stored as 0
+  diag = op_diag(__uint_as_float(rec.y & 0xFFFF0000u), fp[0], fm[0], fp[1], fm[1], fp[2], fm[2]);
+}
 __device__ inline void put_face(const LevelK<double>& l, int d, long long i, double v) {
   l.cf[d][i] = v;
 }

@@ -741,23 +741,6 @@ void launch_coarsest_solve(hipStream_t s, const LevelK<T>& c, const T* InvT) {
 // ---------------------------------------------------------------------------
 // multigrid: smoother, residual, transfers
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ inline T offdiag_sum(const LevelK<T>& l, const int (&c)[3], long long idx) {
-  const int n[3] = {l.nx, l.ny, l.nz};
-  T s = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    int q[3];
-    if (neighbour(c, n, l.per, d, +1, q))
-      s += face_of(l, d, idx) * l.x[cell_index(q[0], q[1], q[2], l.ny, l.nz)];
-    if (neighbour(c, n, l.per, d, -1, q)) {
-      long long Q = cell_index(q[0], q[1], q[2], l.ny, l.nz);
-      s += face_of(l, d, Q) * l.x[Q];
-    }
-  }
-  return s;
-}
-
 // One colour of a red-black Gauss-Seidel sweep (red: i+j+k even).  FINE
 // only gives the finest-level instantiation its own name for profiling.
 template <class T, int FINE>
@@ -767,9 +750,11 @@ __global__ void __launch_bounds__(kBlock) k_rbgs(LevelK<T> l, int color, int zer
     int c[3];
     cell_ijk(idx, l.ny, l.nz, c[0], c[1], c[2]);
     if (((c[0] + c[1] + c[2]) & 1) != color) continue;
+    T off, dg;
+    row_terms(l, c, idx, !zero_init, off, dg);
     T s = l.b[idx];
-    if (!zero_init) s += offdiag_sum(l, c, idx);
-    l.x[idx] = s / diag_of(l, c, idx);
+    if (!zero_init) s += off;
+    l.x[idx] = s / dg;
   }
 }
 
@@ -1007,7 +992,7 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       if (wrap(y0 + ly, l.ny, l.per[1]) < 0 || wrap(z0 + lz, l.nz, l.per[2]) < 0) continue;
       const int q = ly * HZ + lz;
       qs[j] = q;
-      // same order as offdiag_sum: +x, -x, +y, -y, +z, -z
+      // same order as row_terms: +x, -x, +y, -y, +z, -z
       T off = c0c[q] * nxt[q];
       off += c0m[q] * prv[q];
       off += c1[q] * cur[q + HZ];
@@ -1147,7 +1132,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_residual(LevelK<T> l) {
        idx += (long long)blockDim.x * gridDim.x) {
     int c[3];
     cell_ijk(idx, l.ny, l.nz, c[0], c[1], c[2]);
-    l.r[idx] = l.b[idx] - (diag_of(l, c, idx) * l.x[idx] - offdiag_sum(l, c, idx));
+    T off, dg;
+    row_terms(l, c, idx, true, off, dg);
+    l.r[idx] = l.b[idx] - (dg * l.x[idx] - off);
   }
 }
 
@@ -1379,7 +1366,7 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
       for (int j = 0; j < NRES; ++j) {
         const int q = rq[j];
         if (q < 0) continue;
-        // k_mg_residual: b - (diag x - offdiag), offdiag in the order of offdiag_sum
+        // k_mg_residual: b - (diag x - offdiag), offdiag in the order of row_terms
         T off = 0;
         off += c0c[q] * nxt[q];
         off += c0m[q] * prv[q];
