@@ -111,9 +111,10 @@ typedef struct rh_params {
   int32_t smoother;            /* multigrid kernel form: 0 = auto (the red-black sweep   */
                                /* as one marching launch for both colours, and the       */
                                /* residual fused with the restriction, on levels where   */
-                               /* they get >= 2048 workgroups (the sweep below the       */
-                               /* finest level: >= 512); elsewhere one launch per        */
-                               /* colour and separate residual and restriction), 1 =     */
+                               /* they get >= 256 (sweep) / 512 (residual) workgroups,   */
+                               /* with the longest x chunks that keep that many;         */
+                               /* elsewhere one launch per colour and separate residual  */
+                               /* and restriction), 1 =                                  */
                                /* always the separate launches, 2 = the marching         */
                                /* launches on every level their tiles fit (FP32 levels:  */
                                /* nz >= 64, ny >= 16; FP64: nz >= 32, ny >= 8; nx >= 4). */

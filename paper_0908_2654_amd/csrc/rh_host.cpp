@@ -793,10 +793,11 @@ void block_relax(rh_handle* h, int l, bool forward) {
 template <class T>
 void sweep(rh_handle* h, int l, int first_color, int zero_init, bool last = false) {
   LevelK<T>* L = levels<T>(h);
-  // auto: the fused sweep only where it gets enough workgroups to fill the
-  // chip (below the finest level fewer, longer chunks: less re-staging of
-  // each chunk's boundary planes)
-  const long long min_tiles = h->p.smoother == 2 ? 1 : (l == 0 ? 2048 : 512);
+  // auto: the fused sweep where it gets at least one workgroup per CU, with
+  // the longest chunks (up to 32 planes: least re-staging of each chunk's
+  // boundary planes) that keep that many (measured on 128^3: 24.6 us against
+  // 2 x 23 us for the two colour launches; 64^3 levels stay per colour)
+  const long long min_tiles = h->p.smoother == 2 ? 1 : 256;
   if (h->p.smoother != 1 && rbgs_march_fits<T>(L[l], min_tiles)) {
     const bool dots = l == 0 && last && h->dots_wanted;
     if (dots) {
@@ -821,7 +822,7 @@ void sweep(rh_handle* h, int l, int first_color, int zero_init, bool last = fals
 template <class T>
 void residual_restrict(rh_handle* h, int l) {
   LevelK<T>* L = levels<T>(h);
-  const long long min_tiles = h->p.smoother == 2 ? 1 : 2048;
+  const long long min_tiles = h->p.smoother == 2 ? 1 : 512;
   if (h->p.smoother != 1 && resid_restrict_fits<T>(L[l], min_tiles)) {
     Timed tm(h, l == 0 ? KK_MGRES0 : KK_COARSE);
     launch_resid_restrict_march<T>(h->stream, L[l], L[l + 1], min_tiles);
