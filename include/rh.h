@@ -386,7 +386,8 @@ rh_status rh_set_kernel_timing(rh_handle* h, int32_t enable);
  * dot products (class 11 then has no launches), 16 advection substep
  * (rh_advect), 17 its Courant-number reduction, 18 block relaxation around the
  * sources on the finest level, 19 the box inverses of the block smoother
- * (all levels; block relaxation below the finest level counts in 8).  ms / counts are host arrays
+ * (all levels; block relaxation below the finest level counts in 8); 20..22 are used by
+ * the multigroup step (rh_multigroup_get_kernel_timing).  ms / counts are host arrays
  * (either may be NULL); reset != 0 clears the totals afterwards. */
 rh_status rh_get_kernel_timing(rh_handle* h, double* ms, int64_t* counts, int32_t n,
                                int32_t reset);
@@ -520,6 +521,17 @@ rh_status rh_multigroup_residual(rh_multigroup* h, double t_n_s, double dt_s, co
 
 /* Message of the last failed call on h (NULL: of the last failed
  * rh_multigroup_setup / _constants / _workspace_bytes on this thread). */
+/* Per-kernel GPU timing of the multigroup step (as rh_set_kernel_timing /
+ * rh_get_kernel_timing, for every group's handle): the totals are summed
+ * over the groups.  Classes 0..19 as for the grey step (each launch covers
+ * one group's N cells), 20 the local solves over the species (all groups,
+ * one launch), 21 the coupled residuals and operator applications of the
+ * FGMRES solve, 22 its vector work (Gram-Schmidt dot products, basis and
+ * solution updates, the preconditioner's accumulation). */
+rh_status rh_multigroup_set_kernel_timing(rh_multigroup* h, int32_t enable);
+rh_status rh_multigroup_get_kernel_timing(rh_multigroup* h, double* ms, int64_t* counts,
+                                          int32_t n, int32_t reset);
+
 const char* rh_multigroup_last_error(const rh_multigroup* h);
 
 /* Release the handle (not the caller's workspace).  NULL is accepted. */

@@ -19,7 +19,9 @@ KERNEL_CLASSES = ["step_setup", "local_solve", "residual_schur", "finalize", "rb
                   "mg_residual_fine", "restrict_fine", "prolong_fine", "coarse_levels",
                   "pcg_direction", "pcg_update", "pcg_precond", "defect_update", "cast",
                   "rbgs_fine_colour", "rbgs_fine_dots", "advect", "advect_courant",
-                  "block_relax", "block_inverse"]
+                  "block_relax", "block_inverse",
+                  # multigroup step only
+                  "local_groups", "coupled_residual", "krylov"]
 
 RH_OK, RH_EINVAL, RH_ENOMEM, RH_EHIP, RH_ENONFINITE, RH_ENEWTON, RH_ELINEAR = range(7)
 STATUS_NAMES = {0: "RH_OK", 1: "RH_EINVAL", 2: "RH_ENOMEM", 3: "RH_EHIP", 4: "RH_ENONFINITE",
@@ -136,6 +138,9 @@ SIGNATURES = {
     "rh_multigroup_step": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _SP]),
     "rh_multigroup_residual": (_i32, [_vp, _f64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, ctypes.POINTER(_f64)]),
+    "rh_multigroup_set_kernel_timing": (_i32, [_vp, _i32]),
+    "rh_multigroup_get_kernel_timing": (_i32, [_vp, ctypes.POINTER(_f64),
+                                                ctypes.POINTER(ctypes.c_int64), _i32, _i32]),
     "rh_multigroup_last_error": (ctypes.c_char_p, [_vp]),
     "rh_multigroup_destroy": (None, [_vp]),
 }

@@ -284,7 +284,10 @@ rh_status groups_eval(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const GSt
   a.K = h->K; a.kB = h->kB;
   a.fe_out = fe; a.fy_out = fy;
   a.mode = mode;
-  launch_local_groups(h->stream, kg[0], h->gk, a, s0->part);
+  {
+    Timed tm(s0, KK_LOCALG);
+    launch_local_groups(h->stream, kg[0], h->gk, a, s0->part);
+  }
   GHIPCHK(hipGetLastError());
   const double* Ec = mode == 0 ? out.E : cur.E;
   const double* yc = mode == 0 ? out.y : cur.y;
@@ -311,7 +314,10 @@ rh_status groups_eval(rh_multigroup* h, const StepK (&kg)[kMaxGroups], const GSt
     r.diag64 = s->diag64;
     r.op32 = mixed ? s->L32[0].op : nullptr;
     r.fE_out = fE ? fE + g * N : nullptr;
-    launch_residual(h->stream, kg[g], r, s->part);
+    {
+      Timed tm(s, KK_RESID);
+      launch_residual(h->stream, kg[g], r, s->part);
+    }
     GHIPCHK(hipGetLastError());
     const unsigned mask = g == 0 ? kAllSlots
                                  : slot_bit(RS_FE2) | slot_bit(RS_RMAX) | slot_bit(RS_BAD_RES);
@@ -340,7 +346,10 @@ rh_status coupled_residual(rh_multigroup* h, const StepK& k, int g, const double
                            const double* x, double& fe2, double& rmax) {
   rh_handle* s = h->sub[g];
   const double* cf[3] = {s->cf64[0], s->cf64[1], s->cf64[2]};
-  launch_group_coupled(h->stream, k, h->G, g, rhs, s->diag64, cf, h->K, x, h->b, s->part);
+  {
+    Timed tm(s, KK_GCOUPLED);
+    launch_group_coupled(h->stream, k, h->G, g, rhs, s->diag64, cf, h->K, x, h->b, s->part);
+  }
   GHIPCHK(hipGetLastError());
   rh_status st = handle_reductions(s, slot_bit(RS_FE2) | slot_bit(RS_R2) | slot_bit(RS_RMAX));
   if (st != RH_OK) return sub_fail(h, g, st);
@@ -380,7 +389,10 @@ rh_status groups_precondition(rh_multigroup* h, const StepK (&kg)[kMaxGroups], c
     s->keep_coarse = true;
     if (st != RH_OK) return sub_fail(h, g, st);
     its_total += its;
-    launch_xaxpy(h->stream, N, 1.0, x, z + g * N, 0);
+    {
+      Timed tm(h->sub[0], KK_KRYLOV);
+      launch_xaxpy(h->stream, N, 1.0, x, z + g * N, 0);
+    }
     GHIPCHK(hipGetLastError());
   }
   return RH_OK;
@@ -425,7 +437,10 @@ rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double t
   rh_status st = RH_OK;
   for (int restart = 0;; ++restart) {
     // true residual V_0 = rS - S dE and its norm
-    launch_groups_coupled(h->stream, kg[0], G, ops, h->K, h->dE, V, s0->part);
+    {
+      Timed tm(s0, KK_GCOUPLED);
+      launch_groups_coupled(h->stream, kg[0], G, ops, h->K, h->dE, V, s0->part);
+    }
     GHIPCHK(hipGetLastError());
     if ((st = handle_reductions(s0, slot_bit(RS_FE2) | slot_bit(RS_MAG2))) != RH_OK)
       return sub_fail(h, 0, st);
@@ -440,7 +455,10 @@ rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double t
     }
     if (sweeps >= max_sweeps) break;
     const double beta = std::sqrt(rr);
-    launch_wcombine(h->stream, N, G, wk, V, 1.0 / beta, nullptr, 0, 0, none, h->kpart, nullptr);
+    {
+      Timed tm(s0, KK_KRYLOV);
+      launch_wcombine(h->stream, N, G, wk, V, 1.0 / beta, nullptr, 0, 0, none, h->kpart, nullptr);
+    }
     GHIPCHK(hipGetLastError());
     double H[kRestart + 1][kRestart] = {};
     double cs[kRestart] = {}, sn[kRestart] = {}, gv[kRestart + 1] = {};
@@ -450,11 +468,17 @@ rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double t
       if ((st = groups_precondition(h, kg, V + j * GN, Z + j * GN, its_total)) != RH_OK) return st;
       ++sweeps;
       double* Vn = V + (j + 1) * GN;
-      launch_groups_coupled(h->stream, kg[0], G, apply, h->K, Z + j * GN, Vn, s0->part);
+      {
+        Timed tm(s0, KK_GCOUPLED);
+        launch_groups_coupled(h->stream, kg[0], G, apply, h->K, Z + j * GN, Vn, s0->part);
+      }
       GHIPCHK(hipGetLastError());
       // classical Gram-Schmidt, twice
       for (int pass = 0; pass < 2; ++pass) {
-        launch_wdots(h->stream, N, G, wk, Vn, V, GN, j + 1, h->kpart, h->kred_dev);
+        {
+          Timed tm(s0, KK_KRYLOV);
+          launch_wdots(h->stream, N, G, wk, Vn, V, GN, j + 1, h->kpart, h->kred_dev);
+        }
         GHIPCHK(hipGetLastError());
         GHIPCHK(hipStreamSynchronize(h->stream));
         Coefs c{};
@@ -462,14 +486,18 @@ rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double t
           c.c[i] = -hv[i];
           H[i][j] += hv[i];
         }
-        launch_wcombine(h->stream, N, G, wk, Vn, 1.0, V, GN, j + 1, c, h->kpart,
-                        pass == 1 ? h->kred_dev : nullptr);
+        {
+          Timed tm(s0, KK_KRYLOV);
+          launch_wcombine(h->stream, N, G, wk, Vn, 1.0, V, GN, j + 1, c, h->kpart,
+                          pass == 1 ? h->kred_dev : nullptr);
+        }
         GHIPCHK(hipGetLastError());
       }
       GHIPCHK(hipStreamSynchronize(h->stream));
       const double hn = std::sqrt(std::max(hv[0], 0.0));
       H[j + 1][j] = hn;
       if (hn > 0.0) {
+        Timed tm(s0, KK_KRYLOV);
         launch_wcombine(h->stream, N, G, wk, Vn, 1.0 / hn, nullptr, 0, 0, none, h->kpart, nullptr);
         GHIPCHK(hipGetLastError());
       }
@@ -497,7 +525,10 @@ rh_status groups_solve(rh_multigroup* h, const StepK (&kg)[kMaxGroups], double t
       for (int l = i + 1; l < kdim; ++l) t -= H[i][l] * y.c[l];
       y.c[i] = H[i][i] != 0.0 ? t / H[i][i] : 0.0;
     }
-    launch_wcombine(h->stream, N, G, wk, h->dE, 1.0, Z, GN, kdim, y, h->kpart, nullptr);
+    {
+      Timed tm(s0, KK_KRYLOV);
+      launch_wcombine(h->stream, N, G, wk, h->dE, 1.0, Z, GN, kdim, y, h->kpart, nullptr);
+    }
     GHIPCHK(hipGetLastError());
   }
   for (int g = 0; g < G; ++g) h->sub[g]->keep_coarse = false;
@@ -786,6 +817,34 @@ rh_status rh_multigroup_residual(rh_multigroup* h, double t_n, double dt, const 
   st = groups_eval(h, kg, U, nullptr, 0.0, U, false, nH, 1, fE, h->iso ? nullptr : fe, fy, ev);
   if (st != RH_OK) return st;
   if (norm_out) *norm_out = ev.norm;
+  return RH_OK;
+}
+
+rh_status rh_multigroup_set_kernel_timing(rh_multigroup* h, int32_t enable) {
+  if (!h) return RH_EINVAL;
+  for (int g = 0; g < h->G; ++g) {
+    rh_status st = rh_set_kernel_timing(h->sub[g], enable);
+    if (st != RH_OK) return sub_fail(h, g, st);
+  }
+  return RH_OK;
+}
+
+rh_status rh_multigroup_get_kernel_timing(rh_multigroup* h, double* ms, int64_t* counts,
+                                          int32_t n, int32_t reset) {
+  if (!h || n < 1) return RH_EINVAL;
+  const int m = std::min<int>(n, KK_COUNT);
+  if (ms) std::fill(ms, ms + m, 0.0);
+  if (counts) std::fill(counts, counts + m, int64_t(0));
+  for (int g = 0; g < h->G; ++g) {
+    double gm[KK_COUNT];
+    int64_t gc[KK_COUNT];
+    rh_status st = rh_get_kernel_timing(h->sub[g], gm, gc, KK_COUNT, reset);
+    if (st != RH_OK) return sub_fail(h, g, st);
+    for (int i = 0; i < m; ++i) {
+      if (ms) ms[i] += gm[i];
+      if (counts) counts[i] += gc[i];
+    }
+  }
   return RH_OK;
 }
 

@@ -390,38 +390,6 @@ StepK make_step_from(const rh_params& p, const Grey& g, double t_n, double dt) {
 
 StepK make_step(rh_handle* h, double t_n, double dt) { return make_step_from(h->p, h->g, t_n, dt); }
 
-void flush_timing(rh_handle* h) {
-  for (int i = 0; i < h->npool; ++i) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, h->eva[i], h->evb[i]) == hipSuccess) {
-      h->kms[h->pkind[i]] += ms;
-      h->kcount[h->pkind[i]] += 1;
-    }
-  }
-  h->npool = 0;
-  // a failed query must not surface later through hipGetLastError
-  (void)hipGetLastError();
-}
-
-// Brackets one launch with an event pair when timing is on.
-struct Timed {
-  rh_handle* h;
-  int slot = -1;
-  Timed(rh_handle* hh, int kind) : h(hh) {
-    if (!h->timing) return;
-    if (h->npool == rh_handle::kPool) {
-      (void)hipStreamSynchronize(h->stream);
-      flush_timing(h);
-    }
-    slot = h->npool++;
-    h->pkind[slot] = kind;
-    (void)hipEventRecord(h->eva[slot], h->stream);
-  }
-  ~Timed() {
-    if (slot >= 0) (void)hipEventRecord(h->evb[slot], h->stream);
-  }
-};
-
 // Phases of a step (rh_step_stats.t_ms[1..5]).
 enum Phase { PH_SETUP = 1, PH_EVAL = 2, PH_COARSE = 3, PH_VCYCLE = 4, PH_OUTER = 5 };
 
@@ -1073,6 +1041,20 @@ rh_status copy_state(rh_handle* h, double* E, double* e, double* n, const double
 
 // Helpers of the handle-free entry point (rh_noalloc.hip).
 namespace rh {
+
+void flush_timing(rh_handle* h) {
+  for (int i = 0; i < h->npool; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->eva[i], h->evb[i]) == hipSuccess) {
+      h->kms[h->pkind[i]] += ms;
+      h->kcount[h->pkind[i]] += 1;
+    }
+  }
+  h->npool = 0;
+  // a failed query must not surface later through hipGetLastError
+  (void)hipGetLastError();
+}
+
 bool params_valid(const rh_params* p, char* err, size_t n) {
   std::string e;
   if (validate(p, e)) return true;

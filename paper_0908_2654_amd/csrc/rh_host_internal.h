@@ -39,7 +39,10 @@ struct StateBuf {
 enum KernelKind {
   KK_SETUP = 0, KK_LOCAL, KK_RESID, KK_FINALIZE, KK_RBGS0, KK_MGRES0, KK_RESTRICT0, KK_PROLONG0,
   KK_COARSE, KK_PCG_DIR, KK_PCG_UPD, KK_PCG_PRE, KK_DEFECT, KK_CAST, KK_RBGS0C, KK_RBGS0D,
-  KK_ADVECT, KK_ADVECT_C, KK_BLOCK0, KK_BLOCKINV, KK_COUNT
+  KK_ADVECT, KK_ADVECT_C, KK_BLOCK0, KK_BLOCKINV,
+  // multigroup step: local solves over the species, coupled residuals, the
+  // FGMRES vector work (timed on the first group's handle)
+  KK_LOCALG, KK_GCOUPLED, KK_KRYLOV, KK_COUNT
 };
 
 struct rh_handle {
@@ -125,6 +128,30 @@ struct MarkerRange {
   ~MarkerRange() { roctxRangeStop(id); }
   MarkerRange(const MarkerRange&) = delete;
   MarkerRange& operator=(const MarkerRange&) = delete;
+};
+
+// Per-launch timing: fold the completed event pairs of h into its totals.
+void flush_timing(rh_handle* h);
+
+// Brackets one launch on h's stream with an event pair when timing is on.
+struct Timed {
+  rh_handle* h;
+  int slot = -1;
+  Timed(rh_handle* hh, int kind) : h(hh) {
+    if (!h->timing) return;
+    if (h->npool == rh_handle::kPool) {
+      (void)hipStreamSynchronize(h->stream);
+      flush_timing(h);
+    }
+    slot = h->npool++;
+    h->pkind[slot] = kind;
+    (void)hipEventRecord(h->eva[slot], h->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(h->evb[slot], h->stream);
+  }
+  Timed(const Timed&) = delete;
+  Timed& operator=(const Timed&) = delete;
 };
 
 // The per-step scalars of a step on handle h (its grey constants).

@@ -351,6 +351,19 @@ class MultigroupSolver:
         _lib.check_multigroup(s, self._h)
         return st.as_dict()
 
+    def set_kernel_timing(self, enable: bool):
+        _lib.check_multigroup(lib.rh_multigroup_set_kernel_timing(self._h, int(bool(enable))),
+                              self._h)
+
+    def kernel_timing(self, reset=True) -> dict:
+        """{class: (total ms, launches)} since the last reset, summed over the groups."""
+        n = len(_lib.KERNEL_CLASSES)
+        ms = (_F64 * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _lib.check_multigroup(lib.rh_multigroup_get_kernel_timing(self._h, ms, cnt, n,
+                                                                  int(bool(reset))), self._h)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.KERNEL_CLASSES)}
+
     def residual(self, t, dt, nH, src, Un, U):
         """f(U) of the step from U^n = (E, e, y): returns (fE, fe, fy, norm)."""
         En, en, yn = Un
