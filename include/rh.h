@@ -519,8 +519,6 @@ rh_status rh_multigroup_residual(rh_multigroup* h, double t_n_s, double dt_s, co
                                  const double* y, double* fE, double* fe, double* fy,
                                  double* norm_out);
 
-/* Message of the last failed call on h (NULL: of the last failed
- * rh_multigroup_setup / _constants / _workspace_bytes on this thread). */
 /* Per-kernel GPU timing of the multigroup step (as rh_set_kernel_timing /
  * rh_get_kernel_timing, for every group's handle): the totals are summed
  * over the groups.  Classes 0..19 as for the grey step (each launch covers
@@ -532,6 +530,8 @@ rh_status rh_multigroup_set_kernel_timing(rh_multigroup* h, int32_t enable);
 rh_status rh_multigroup_get_kernel_timing(rh_multigroup* h, double* ms, int64_t* counts,
                                           int32_t n, int32_t reset);
 
+/* Message of the last failed call on h (NULL: of the last failed
+ * rh_multigroup_setup / _constants / _workspace_bytes on this thread). */
 const char* rh_multigroup_last_error(const rh_multigroup* h);
 
 /* Release the handle (not the caller's workspace).  NULL is accepted. */
