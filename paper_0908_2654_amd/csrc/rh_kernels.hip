@@ -807,10 +807,11 @@ struct MarchTile<double> {
 };
 // Prefetch registers of one staged coefficient slot of a marching kernel:
 // FP64 levels hold the diagonal and the three + faces, FP32 levels the raw
-// packed record, decoded only when it is staged to LDS (so the loads in
-// flight are not waited for early).  In LDS the "diagonal" plane holds the
-// diagonal (FP64) or the shift (FP32; the diagonal is then op_diag of the
-// staged shift and faces).
+// packed record, split into its bfloat16 halves only when it is staged to
+// LDS (so the loads in flight are not waited for early; the halves stay
+// bfloat16 in LDS, half the bytes of FP32 staging).  In LDS the "diagonal"
+// plane holds the diagonal (FP64) or the shift (FP32; the diagonal is then
+// op_diag of the staged shift and faces).
 template <class T>
 struct CoefRegs {
   T d, f0, f1, f2;
@@ -832,18 +833,22 @@ __device__ inline void load_coef(const LevelK<float>& l, long long P, bool ok, b
                                  CoefRegs<float>& r) {
   r.raw = ok ? reinterpret_cast<const uint2*>(l.op)[P] : make_uint2(0u, 0u);
 }
-__device__ inline double coef_f0(const CoefRegs<double>& r) { return r.f0; }
-__device__ inline double coef_f1(const CoefRegs<double>& r) { return r.f1; }
-__device__ inline double coef_f2(const CoefRegs<double>& r) { return r.f2; }
-__device__ inline double coef_d(const CoefRegs<double>& r) { return r.d; }
-__device__ inline float coef_f0(const CoefRegs<float>& r) { return __uint_as_float(r.raw.x << 16); }
-__device__ inline float coef_f1(const CoefRegs<float>& r) {
-  return __uint_as_float(r.raw.x & 0xFFFF0000u);
-}
-__device__ inline float coef_f2(const CoefRegs<float>& r) { return __uint_as_float(r.raw.y << 16); }
-__device__ inline float coef_d(const CoefRegs<float>& r) {
-  return __uint_as_float(r.raw.y & 0xFFFF0000u);
-}
+// The same values in the form they are staged to LDS: FP32 levels keep the
+// bfloat16 halves (2 bytes per value; read back with lv), FP64 levels the
+// doubles.
+__device__ inline uint16_t coef_r0(const CoefRegs<float>& r) { return (uint16_t)(r.raw.x & 0xFFFFu); }
+__device__ inline uint16_t coef_r1(const CoefRegs<float>& r) { return (uint16_t)(r.raw.x >> 16); }
+__device__ inline uint16_t coef_r2(const CoefRegs<float>& r) { return (uint16_t)(r.raw.y & 0xFFFFu); }
+__device__ inline uint16_t coef_rd(const CoefRegs<float>& r) { return (uint16_t)(r.raw.y >> 16); }
+__device__ inline double coef_r0(const CoefRegs<double>& r) { return r.f0; }
+__device__ inline double coef_r1(const CoefRegs<double>& r) { return r.f1; }
+__device__ inline double coef_r2(const CoefRegs<double>& r) { return r.f2; }
+__device__ inline double coef_rd(const CoefRegs<double>& r) { return r.d; }
+__device__ inline float lv(uint16_t h) { return bf16_value(h); }
+__device__ inline double lv(double v) { return v; }
+template <class T>
+using staged_t = typename std::conditional<std::is_same<T, float>::value, uint16_t, T>::type;
+
 // Diagonal of a staged cell from the staged "diagonal" value and the six
 // staged faces (+x, -x, +y, -y, +z, -z).
 __device__ inline double staged_diag(double d, double, double, double, double, double, double) {
@@ -885,8 +890,10 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
   constexpr int NRED = ((TY + 2) * (TZ + 2) / 2 + NT - 1) / NT;
   constexpr int NBLK = (TY * TZ / 2 + NT - 1) / NT;
   __shared__ T xs[4 * PL];
-  __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes p-1, p)
-  __shared__ T c0s[3 * CP];    // x faces (planes p-2, p-1, p)
+  using CT = staged_t<T>;
+  __shared__ T bsh[2 * CP];     // right-hand side (planes p-1, p)
+  __shared__ CT cs[3][2 * CP];  // diag / shift, y faces, z faces (planes p-1, p)
+  __shared__ CT c0s[3 * CP];    // x faces (planes p-2, p-1, p)
   const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
   int bid = xcd_tile(blockIdx.x, gridDim.x);
   const int tz = bid % ntz;
@@ -954,12 +961,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       const int t = tid + j * NT;
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
-      c0s[s3 + li] = coef_f0(B.k[j]);
+      c0s[s3 + li] = coef_r0(B.k[j]);
       if (all) {
-        cs[0][s2 + li] = B.b[j];
-        cs[1][s2 + li] = coef_d(B.k[j]);
-        cs[2][s2 + li] = coef_f1(B.k[j]);
-        cs[3][s2 + li] = coef_f2(B.k[j]);
+        bsh[s2 + li] = B.b[j];
+        cs[0][s2 + li] = coef_rd(B.k[j]);
+        cs[1][s2 + li] = coef_r1(B.k[j]);
+        cs[2][s2 + li] = coef_r2(B.k[j]);
       }
     }
   };
@@ -972,12 +979,12 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
     const T* prv = xs + pmod(p - 1, 4) * PL;
     const T* nxt = xs + pmod(p + 1, 4) * PL;
     const int s2 = pmod(p, 2) * CP;
-    const T* cb = cs[0] + s2;
-    const T* cd = cs[1] + s2;
-    const T* c1 = cs[2] + s2;
-    const T* c2 = cs[3] + s2;
-    const T* c0c = c0s + pmod(p, 3) * CP;
-    const T* c0m = c0s + pmod(p - 1, 3) * CP;
+    const T* cb = bsh + s2;
+    const CT* cd = cs[0] + s2;
+    const CT* c1 = cs[1] + s2;
+    const CT* c2 = cs[2] + s2;
+    const CT* c0c = c0s + pmod(p, 3) * CP;
+    const CT* c0m = c0s + pmod(p - 1, 3) * CP;
     const int half = ez / 2;
     int qs[NP];
     T nv[NP];
@@ -993,13 +1000,15 @@ k_rbgs_march(LevelK<T> l, int first_color, int zero_init, int xc, double sigma,
       const int q = ly * HZ + lz;
       qs[j] = q;
       // same order as row_terms: +x, -x, +y, -y, +z, -z
-      T off = c0c[q] * nxt[q];
-      off += c0m[q] * prv[q];
-      off += c1[q] * cur[q + HZ];
-      off += c1[q - HZ] * cur[q - HZ];
-      off += c2[q] * cur[q + 1];
-      off += c2[q - 1] * cur[q - 1];
-      nv[j] = (cb[q] + off) / staged_diag(cd[q], c0c[q], c0m[q], c1[q], c1[q - HZ], c2[q], c2[q - 1]);
+      const T fxp = lv(c0c[q]), fxm = lv(c0m[q]), fyp = lv(c1[q]), fym = lv(c1[q - HZ]);
+      const T fzp = lv(c2[q]), fzm = lv(c2[q - 1]);
+      T off = fxp * nxt[q];
+      off += fxm * prv[q];
+      off += fyp * cur[q + HZ];
+      off += fym * cur[q - HZ];
+      off += fzp * cur[q + 1];
+      off += fzm * cur[q - 1];
+      nv[j] = (cb[q] + off) / staged_diag(lv(cd[q]), fxp, fxm, fyp, fym, fzp, fzm);
     }
 #pragma unroll
     for (int j = 0; j < NP; ++j)
@@ -1207,8 +1216,10 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
   constexpr int NCC = (TY / 2) * (TZ / 2);                 // coarse cells per tile
   static_assert(NCC <= NT, "one coarse cell per thread");
   __shared__ T xs[4 * PL];
-  __shared__ T cs[4][2 * CP];  // b, diag, y faces, z faces (planes i, i+1)
-  __shared__ T c0s[3 * CP];    // x faces (planes i-1, i, i+1)
+  using CT = staged_t<T>;
+  __shared__ T bsh[2 * CP];     // right-hand side (planes i, i+1)
+  __shared__ CT cs[3][2 * CP];  // diag / shift, y faces, z faces (planes i, i+1)
+  __shared__ CT c0s[3 * CP];    // x faces (planes i-1, i, i+1)
   __shared__ T rs[2][CP];      // residual planes (same coordinates)
   const int ntz = (l.nz + TZ - 1) / TZ, nty = (l.ny + TY - 1) / TY;
   int bid = xcd_tile(blockIdx.x, gridDim.x);
@@ -1306,12 +1317,12 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
       if (t >= CN) continue;
       const int li = (t / CZ) * HZ + t % CZ;
       const bool ok = pok && coff[j] >= 0;
-      c0s[s3 + li] = ok ? coef_f0(B.k[j]) : T(0);
+      c0s[s3 + li] = ok ? coef_r0(B.k[j]) : CT(0);
       if (all) {
-        cs[0][s2 + li] = ok ? B.b[j] : T(0);
-        cs[1][s2 + li] = ok ? coef_d(B.k[j]) : T(0);
-        cs[2][s2 + li] = ok ? coef_f1(B.k[j]) : T(0);
-        cs[3][s2 + li] = ok ? coef_f2(B.k[j]) : T(0);
+        bsh[s2 + li] = ok ? B.b[j] : T(0);
+        cs[0][s2 + li] = ok ? coef_rd(B.k[j]) : CT(0);
+        cs[1][s2 + li] = ok ? coef_r1(B.k[j]) : CT(0);
+        cs[2][s2 + li] = ok ? coef_r2(B.k[j]) : CT(0);
       }
     }
   };
@@ -1355,26 +1366,28 @@ k_resid_restrict_march(LevelK<T> l, LevelK<T> c, int xc) {
       const T* prv = xs + pmod(i - 1, 4) * PL;
       const T* nxt = xs + pmod(i + 1, 4) * PL;
       const int s2 = pmod(i, 2) * CP;
-      const T* cb = cs[0] + s2;
-      const T* cd = cs[1] + s2;
-      const T* c1 = cs[2] + s2;
-      const T* c2 = cs[3] + s2;
-      const T* c0c = c0s + pmod(i, 3) * CP;
-      const T* c0m = c0s + pmod(i - 1, 3) * CP;
+      const T* cb = bsh + s2;
+      const CT* cd = cs[0] + s2;
+      const CT* c1 = cs[1] + s2;
+      const CT* c2 = cs[2] + s2;
+      const CT* c0c = c0s + pmod(i, 3) * CP;
+      const CT* c0m = c0s + pmod(i - 1, 3) * CP;
       T* r = rs[i & 1];
 #pragma unroll
       for (int j = 0; j < NRES; ++j) {
         const int q = rq[j];
         if (q < 0) continue;
         // k_mg_residual: b - (diag x - offdiag), offdiag in the order of row_terms
+        const T fxp = lv(c0c[q]), fxm = lv(c0m[q]), fyp = lv(c1[q]), fym = lv(c1[q - HZ]);
+        const T fzp = lv(c2[q]), fzm = lv(c2[q - 1]);
         T off = 0;
-        off += c0c[q] * nxt[q];
-        off += c0m[q] * prv[q];
-        off += c1[q] * cur[q + HZ];
-        off += c1[q - HZ] * cur[q - HZ];
-        off += c2[q] * cur[q + 1];
-        off += c2[q - 1] * cur[q - 1];
-        const T dq = staged_diag(cd[q], c0c[q], c0m[q], c1[q], c1[q - HZ], c2[q], c2[q - 1]);
+        off += fxp * nxt[q];
+        off += fxm * prv[q];
+        off += fyp * cur[q + HZ];
+        off += fym * cur[q - HZ];
+        off += fzp * cur[q + 1];
+        off += fzm * cur[q - 1];
+        const T dq = staged_diag(lv(cd[q]), fxp, fxm, fyp, fym, fzp, fzm);
         r[q] = cb[q] - (dq * cur[q] - off);
       }
     }
